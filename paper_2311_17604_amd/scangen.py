@@ -1,0 +1,260 @@
+"""Seeded synthetic terrestrial-LiDAR scans (input generator only).
+
+This module produces the int32 millimetre point clouds that both the HIP path
+and the CPU oracle consume.  It holds none of the decimation arithmetic: it
+casts rays from a tripod-mounted station against a box scene and quantises the
+hit points.
+
+Scan model (the paper's workloads are stationary LiDAR scans of buildings,
+taken from a tripod about 1.5 m above the ground, merged from 2-38 stations,
+with an equal number of samples per elevation row so that density peaks at
+the poles; Introduction, Sec. 6):
+
+* station at height 1500 mm;
+* row i of R: elevation -60 deg + 150 deg * i / (R - 1);
+* column j of C: azimuth 360 deg * j / C;
+* range noise N(0, sigma) mm added along the ray, sigma = 2 mm;
+* xyz rounded to the nearest millimetre (numpy ``rint``) and stored as int32.
+
+Every ray must hit so that the point count equals R * C: the scene is closed
+by an axis-aligned box whose floor is the ground plane z = 0.
+
+All randomness comes from ``numpy.random.Generator(PCG64(seed))``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+DEG = math.pi / 180.0
+
+
+@dataclass(frozen=True)
+class Scene:
+    """Solid axis-aligned boxes (mm) inside a closing box (mm)."""
+
+    box_lo: np.ndarray  # [nb, 3] float64
+    box_hi: np.ndarray  # [nb, 3] float64
+    close_lo: np.ndarray  # [3]
+    close_hi: np.ndarray  # [3]
+
+
+def _ray_dirs(rows: int, cols: int) -> tuple[np.ndarray, np.ndarray]:
+    el = (-60.0 + 150.0 * np.arange(rows, dtype=np.float64) / max(rows - 1, 1)) * DEG
+    az = (360.0 * np.arange(cols, dtype=np.float64) / cols) * DEG
+    return el, az
+
+
+def wall_scene(rng: np.random.Generator, nboxes: int, rmin_m: float, rmax_m: float,
+               close_half_m: float, close_height_m: float,
+               centres_xy_mm: np.ndarray | None = None) -> Scene:
+    """Random wall-like boxes: 0.2-0.5 m thick, 2-20 m long, 2-10 m high.
+
+    Each box is placed at a distance drawn from U[rmin, rmax] metres (and a
+    uniform bearing) from a random anchor in ``centres_xy_mm`` (the station
+    positions; the origin if None), resting on the ground.  Boxes that would
+    contain any station (with a 1 m margin) are redrawn.
+    """
+    if centres_xy_mm is None:
+        centres_xy_mm = np.zeros((1, 2))
+    lo = np.zeros((nboxes, 3))
+    hi = np.zeros((nboxes, 3))
+    b = 0
+    while b < nboxes:
+        thick = rng.uniform(200.0, 500.0)
+        length = rng.uniform(2000.0, 20000.0)
+        height = rng.uniform(2000.0, 10000.0)
+        dist = rng.uniform(rmin_m, rmax_m) * 1000.0
+        bearing = rng.uniform(0.0, 2.0 * math.pi)
+        along_x = rng.uniform() < 0.5
+        anchor = centres_xy_mm[rng.integers(0, len(centres_xy_mm))]
+        cx = anchor[0] + dist * math.cos(bearing)
+        cy = anchor[1] + dist * math.sin(bearing)
+        sx, sy = (length, thick) if along_x else (thick, length)
+        blo = np.array([cx - sx / 2, cy - sy / 2, 0.0])
+        bhi = np.array([cx + sx / 2, cy + sy / 2, height])
+        # keep every station outside every box, with a margin
+        inside = ((centres_xy_mm[:, 0] > blo[0] - 1000) & (centres_xy_mm[:, 0] < bhi[0] + 1000) &
+                  (centres_xy_mm[:, 1] > blo[1] - 1000) & (centres_xy_mm[:, 1] < bhi[1] + 1000))
+        if inside.any():
+            continue
+        lo[b], hi[b] = blo, bhi
+        b += 1
+    ch = close_half_m * 1000.0
+    cmin = centres_xy_mm.min(axis=0)
+    cmax = centres_xy_mm.max(axis=0)
+    close_lo = np.array([cmin[0] - ch, cmin[1] - ch, 0.0])
+    close_hi = np.array([cmax[0] + ch, cmax[1] + ch, close_height_m * 1000.0])
+    return Scene(lo, hi, close_lo, close_hi)
+
+
+def _cast(origin: np.ndarray, d: np.ndarray, scene: Scene) -> np.ndarray:
+    """Range (mm) to the first hit of rays origin + t d (d unit, [m, 3])."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = 1.0 / d
+        # exit distance from the closing box (origin is inside it)
+        t1 = (scene.close_lo[None, :] - origin[None, :]) * inv
+        t2 = (scene.close_hi[None, :] - origin[None, :]) * inv
+        tfar = np.where(np.isnan(np.maximum(t1, t2)), np.inf, np.maximum(t1, t2))
+        best = tfar.min(axis=1)
+        for b in range(scene.box_lo.shape[0]):
+            a1 = (scene.box_lo[b][None, :] - origin[None, :]) * inv
+            a2 = (scene.box_hi[b][None, :] - origin[None, :]) * inv
+            tmin = np.minimum(a1, a2)
+            tmax = np.maximum(a1, a2)
+            tmin = np.where(np.isnan(tmin), -np.inf, tmin)
+            tmax = np.where(np.isnan(tmax), np.inf, tmax)
+            tn = tmin.max(axis=1)
+            tf = tmax.min(axis=1)
+            hit = (tn <= tf) & (tn > 0.0)
+            best = np.where(hit & (tn < best), tn, best)
+    return best
+
+
+def scan_station(rows: int, cols: int, station_xy_mm: tuple[float, float], scene: Scene,
+                 rng: np.random.Generator, sigma_mm: float = 2.0, height_mm: float = 1500.0,
+                 chunk_rows: int | None = None) -> np.ndarray:
+    """One station's R x C scan as int32 [R*C, 3], row-major (row, column)."""
+    el, az = _ray_dirs(rows, cols)
+    origin = np.array([station_xy_mm[0], station_xy_mm[1], height_mm], dtype=np.float64)
+    cos_az, sin_az = np.cos(az), np.sin(az)
+    out = np.empty((rows * cols, 3), dtype=np.int32)
+    if chunk_rows is None:
+        chunk_rows = max(1, (1 << 20) // cols)
+    for r0 in range(0, rows, chunk_rows):
+        r1 = min(rows, r0 + chunk_rows)
+        ce = np.cos(el[r0:r1])[:, None]
+        se = np.sin(el[r0:r1])[:, None]
+        d = np.stack([np.broadcast_to(ce * cos_az[None, :], (r1 - r0, cols)),
+                      np.broadcast_to(ce * sin_az[None, :], (r1 - r0, cols)),
+                      np.broadcast_to(se, (r1 - r0, cols))], axis=-1).reshape(-1, 3)
+        t = _cast(origin, d, scene)
+        t = t + rng.normal(0.0, sigma_mm, size=t.shape[0])
+        p = origin[None, :] + t[:, None] * d
+        out[r0 * cols:r1 * cols] = np.rint(p).astype(np.int32)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# the five workload configurations
+# ----------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    xyz: np.ndarray          # int32 [n, 3]
+    k: int
+    keep: int
+    offsets: np.ndarray | None = None   # int64 [nscan+1] for batches
+    keeps: np.ndarray | None = None     # int64 [nscan] for batches
+
+
+def single_scan(rows: int, cols: int, nboxes: int, rmin_m: float, rmax_m: float,
+                close_half_m: float, seed: int, close_height_m: float | None = None,
+                sigma_mm: float = 2.0) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if close_height_m is None:
+        close_height_m = max(20.0, close_half_m / 2.0)
+    scene = wall_scene(rng, nboxes, rmin_m, rmax_m, close_half_m, close_height_m)
+    return scan_station(rows, cols, (0.0, 0.0), scene, rng, sigma_mm)
+
+
+def place_stations(rng: np.random.Generator, count: int, square_m: float,
+                   dmin_m: float = 30.0, dmax_m: float = 80.0) -> np.ndarray:
+    """Stations by rejection: each 30-80 m from its nearest earlier station,
+    at least 30 m from all of them, inside a square of side ``square_m``."""
+    half = square_m * 500.0
+    st = [np.zeros(2)]
+    tries = 0
+    while len(st) < count:
+        tries += 1
+        if tries > 1_000_000:
+            raise RuntimeError("station placement failed")
+        c = rng.uniform(-half, half, size=2)
+        dist = np.sqrt(((np.array(st) - c) ** 2).sum(axis=1))
+        if dist.min() >= dmin_m * 1000 and dist.min() <= dmax_m * 1000:
+            st.append(c)
+    return np.array(st)
+
+
+def multi_station(stations: int, rows: int, cols: int, nboxes: int, square_m: float,
+                  seed: int, sigma_mm: float = 2.0) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    st = place_stations(rng, stations, square_m)
+    scene = wall_scene(rng, nboxes, 2.0, 50.0, 60.0, 40.0, centres_xy_mm=st)
+    parts = [scan_station(rows, cols, (s[0], s[1]), scene, rng, sigma_mm) for s in st]
+    return np.concatenate(parts, axis=0)
+
+
+def config(idx: int, scale: float = 1.0, seed: int | None = None) -> Workload:
+    """Workload ``idx`` (1-5).  ``scale`` < 1 shrinks the ray grid (rows and
+    columns by sqrt(scale)) for quick tests; 1.0 is the stated size."""
+    def grid(r, c):
+        f = math.sqrt(scale)
+        return max(2, int(round(r * f))), max(2, int(round(c * f)))
+
+    if idx == 1:
+        r, c = grid(500, 400)
+        xyz = single_scan(r, c, 6, 2.0, 50.0, 50.0, 1 if seed is None else seed)
+        n = xyz.shape[0]
+        keep = n // 4
+        return Workload("scan-200k-k8-keep25", xyz, 8, keep)
+    if idx == 2:
+        r, c = grid(5000, 4000)
+        xyz = single_scan(r, c, 40, 2.0, 120.0, 120.0, 2 if seed is None else seed)
+        n = xyz.shape[0]
+        return Workload("scan-20M-k16-keep10", xyz, 16, n // 10)
+    if idx == 3:
+        r, c = grid(10000, 5000)
+        xyz = multi_station(10, r, c, 60, 400.0, 3 if seed is None else seed)
+        n = xyz.shape[0]
+        return Workload("merged-10st-500M-k8-keep5", xyz, 8, n // 20)
+    if idx == 4:
+        return batch_config(4096 if scale >= 1.0 else max(2, int(4096 * scale)),
+                            scale=1.0 if scale >= 1.0 else scale, base_seed=10000 if seed is None else seed)
+    if idx == 5:
+        r, c = grid(10000, 5000)
+        xyz = multi_station(40, r, c, 200, 1000.0, 5 if seed is None else seed)
+        n = xyz.shape[0]
+        return Workload("merged-40st-2B-k8-keep2", xyz, 8, n // 50)
+    raise ValueError(idx)
+
+
+def batch_scan_shape(seed: int, size_scale: float = 1.0) -> tuple[int, int, float]:
+    """(rows, cols, keep_ratio) of batch scan ``seed``: n log-uniform in
+    [1e4, 2e6], aspect log-uniform in [1/2, 2], keep ratio U[0.1, 0.5]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = math.exp(rng.uniform(math.log(1e4), math.log(2e6))) * size_scale
+    aspect = math.exp(rng.uniform(math.log(0.5), math.log(2.0)))
+    rows = max(2, int(round(math.sqrt(n * aspect))))
+    cols = max(2, int(round(n / rows)))
+    ratio = rng.uniform(0.1, 0.5)
+    return rows, cols, ratio
+
+
+def batch_scan(seed: int, size_scale: float = 1.0) -> tuple[np.ndarray, int]:
+    rows, cols, ratio = batch_scan_shape(seed, size_scale)
+    xyz = single_scan(rows, cols, 6, 2.0, 50.0, 50.0, seed + 7_000_000)
+    n = xyz.shape[0]
+    return xyz, max(1, int(math.floor(ratio * n)))
+
+
+def batch_config(nscan: int, scale: float = 1.0, base_seed: int = 10000) -> Workload:
+    parts, keeps = [], []
+    for s in range(nscan):
+        xyz, keep = batch_scan(base_seed + s, scale)
+        parts.append(xyz)
+        keeps.append(keep)
+    offs = np.zeros(nscan + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([p.shape[0] for p in parts])
+    return Workload(f"batch-{nscan}scans-k8", np.concatenate(parts), 8, int(sum(keeps)),
+                    offsets=offs, keeps=np.array(keeps, dtype=np.int64))
+
+
+def random_cloud(n: int, box_mm: int, seed: int) -> np.ndarray:
+    """Uniform integer points in [0, box_mm)^3: small boxes give many
+    duplicates and distance ties."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(0, box_mm, size=(n, 3), dtype=np.int64).astype(np.int32)
