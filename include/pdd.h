@@ -1,0 +1,158 @@
+/*
+ * pdd.h -- C ABI of libpdd, Poisson-disk decimation of int32 point clouds on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * The method (arXiv 2311.17604):
+ *   - cost of a point p (Eq. 11, Sec. 4.2): the sum of 1 / d(p, p')^2 over
+ *     its k nearest remaining neighbours p';
+ *   - greedy removal (Sec. 4, Sec. 4.2): remove the remaining point of highest
+ *     cost, update the costs its removal changes, repeat until exactly the
+ *     requested number of points is left (Sec. 3: |C'| = lambda |C| with
+ *     lambda = m / |C|).
+ *
+ * Exact integer reading used throughout (the paper's Eq. 11 is real-valued
+ * and silent on ties and coincident points):
+ *   d2(i, j) = sum over axes of (P_i - P_j)^2, int64, P in int32 millimetres;
+ *   term(D)  = floor(2^56 / D) for D >= 1, 2^58 for D = 0;
+ *   W(i)     = sum of term over the min(k, alive - 1) smallest d2 from i to
+ *              the other alive points (uint64; k <= 32 keeps it below 2^64);
+ *   key(i)   = (W descending, original index ascending); the greedy removes
+ *              the highest key.  Results are therefore unique, and the
+ *              library returns them bit for bit.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are DEVICE pointers on the context's device; the
+ *     caller allocates and owns them; the library never frees or keeps them
+ *     after the call returns.
+ *   - Points are int32 x, y, z (mm) at a byte stride of 12 (packed xyz) or
+ *     16 (xyz + 4 bytes of attributes, e.g. RGB + pad), first point at d_xyz.
+ *   - Per-axis extent (max - min) must be < 2^21 mm (PDD_ERANGE otherwise).
+ *   - Work runs on the context's stream.  pdd_decimate and
+ *     pdd_decimate_batch synchronise that stream before returning;
+ *     pdd_knn_cost returns once its work is enqueued.
+ *   - Return value is a status code (PDD_OK = 0).  On error the output
+ *     buffers' contents are unspecified, but nothing is written outside
+ *     them.  No C++ exception crosses this interface.
+ */
+#ifndef PDD_H
+#define PDD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PDD_OK = 0,
+    PDD_EINVAL = 1,    /* bad argument: sizes, k, keep, null pointers */
+    PDD_ERANGE = 2,    /* coordinate extent >= 2^21 mm on some axis */
+    PDD_ENOMEM = 3,    /* device allocation failed */
+    PDD_EHIP = 4,      /* a HIP runtime call failed (see pdd_last_error) */
+    PDD_EINTERNAL = 5  /* internal invariant violated (a bug) */
+};
+
+typedef struct pdd_ctx pdd_ctx;   /* device, stream, scratch pool */
+typedef struct pdd_grid pdd_grid; /* Morton-sorted points + voxel cell table, owned by a ctx */
+
+/* Options of a decimation.  A zero field takes the default. */
+typedef struct {
+    int32_t k;              /* neighbours in the cost, 1..32 (no default: required) */
+    int32_t b;              /* extra buffered neighbours, k + b <= 32 (default: 8, capped) */
+    int32_t voxel_log2;     /* cell edge = 2^voxel_log2 mm, 2..20 (default: chosen from density) */
+    float round_frac;       /* share of alive points ranked per removal round, (0, 1] (default 0.03) */
+    int32_t point_stride;   /* bytes between points: 12 or 16 (default 12) */
+    int32_t flags;          /* PDD_F_* bits */
+    int32_t reserved[4];
+} pdd_opts;
+
+#define PDD_F_CHECK 1       /* extra device-side invariant checks (slower) */
+#define PDD_F_TIMING 2      /* record HIP events per phase (see pdd_last_timing) */
+
+/* Create a context on HIP device `hip_device` that enqueues its work on
+ * `hip_stream` (a hipStream_t; NULL = the null stream).  *out receives the
+ * handle.  Errors: PDD_EINVAL (out NULL), PDD_EHIP. */
+int pdd_ctx_create(pdd_ctx **out, int hip_device, void *hip_stream);
+
+/* Release a context, its grids and scratch memory.  NULL is a no-op. */
+void pdd_ctx_destroy(pdd_ctx *ctx);
+
+/*
+ * Voxel grid (Sec. 5: the cloud is voxelised and neighbours are searched in
+ * the point's voxel and the adjacent ones).  Points are ordered by the
+ * 63-bit Morton code of their coordinates relative to the cloud's minimum
+ * corner; cells are the runs of equal code >> (3 * voxel_log2).  The grid
+ * keeps a copy of the points; d_xyz may be freed after the call returns.
+ *   d_xyz, n, stride : input points (n >= 2, stride 12 or 16)
+ *   voxel_log2       : cell edge 2^voxel_log2 mm (2..20), 0 = automatic
+ *   out              : receives the grid handle (free with pdd_grid_free)
+ * Synchronises the stream (the cell count sizes the cell table).
+ * Errors: PDD_EINVAL, PDD_ERANGE, PDD_ENOMEM, PDD_EHIP.
+ */
+int pdd_build_grid(pdd_ctx *ctx, const int32_t *d_xyz, int64_t n, int32_t stride,
+                   int32_t voxel_log2, pdd_grid **out);
+
+/* Free a grid.  NULL is a no-op. */
+void pdd_grid_free(pdd_ctx *ctx, pdd_grid *grid);
+
+/* Number of occupied cells and the voxel_log2 of a grid (either may be NULL). */
+int pdd_grid_info(const pdd_grid *grid, int64_t *ncells, int32_t *voxel_log2);
+
+/*
+ * k-nearest-neighbour cost of every point of a grid over all its points
+ * (Eq. 11 in the exact reading above).  Row i of each output belongs to the
+ * input point i (original order).
+ *   k, b    : 1 <= k, k + b <= 32
+ *   d_nbr   : [n * (k+b)] int32 or NULL: original indices of the k+b nearest,
+ *             ascending d2; -1 past the end when n - 1 < k + b.  Among equal
+ *             d2 the order and, at the last place, the choice of point are
+ *             unspecified.
+ *   d_r2k   : [n] int64 or NULL: d2 of the min(k, n-1)-th nearest
+ *   d_cost  : [n] uint64: W over the min(k, n-1) nearest
+ * Errors: PDD_EINVAL, PDD_ENOMEM, PDD_EHIP.
+ */
+int pdd_knn_cost(pdd_ctx *ctx, const pdd_grid *grid, int32_t k, int32_t b, int32_t *d_nbr,
+                 int64_t *d_r2k, uint64_t *d_cost);
+
+/*
+ * Greedy decimation (Sec. 4, Sec. 4.2) to exactly keep_count points.
+ *   d_xyz, n        : input points (n >= 2), stride opts->point_stride
+ *   keep_count      : 1..n points to keep
+ *   opts            : k required; other fields 0 for defaults
+ *   d_kept          : [keep_count] int32: kept original indices, ascending
+ *   d_order         : [n - keep_count] int32 or NULL: removed indices in the
+ *                     sequential greedy's removal order
+ *   d_order_cost    : [n - keep_count] uint64 or NULL: W of each removed
+ *                     point at its removal
+ * The result equals the sequential greedy's bit for bit (removal happens in
+ * rounds that provably commute with it).  Synchronises the stream.
+ * Errors: PDD_EINVAL, PDD_ERANGE, PDD_ENOMEM, PDD_EHIP, PDD_EINTERNAL.
+ */
+int pdd_decimate(pdd_ctx *ctx, const int32_t *d_xyz, int64_t n, int64_t keep_count,
+                 const pdd_opts *opts, int32_t *d_kept, int32_t *d_order, uint64_t *d_order_cost);
+
+/* Counters of the last pdd_decimate on this context, written to stats[0..n):
+ *   0 rounds, 1 re-searches (buffer exhausted), 2 rho searches, 3 reverse-list
+ *   rebuilds, 4 fallback searches in the initial k-NN, 5 voxel_log2 used,
+ *   6 k+b used, 7 touched (re-costed) points.
+ * Returns the number of counters written. */
+int pdd_last_stats(const pdd_ctx *ctx, int64_t *stats, int n);
+
+/* Phase durations in ms of the last pdd_decimate on this context that ran
+ * with PDD_F_TIMING, from HIP events recorded on the context's stream,
+ * written to ms[0..n): 0 grid build, 1 initial k-NN cost kernel, 2 reverse
+ * lists, 3 removal rounds, 4 finalisation (kept set and removal order).
+ * Returns the number written. */
+int pdd_last_timing(const pdd_ctx *ctx, float *ms, int n);
+
+/* Static description of a status code. */
+const char *pdd_strerror(int status);
+
+/* Text of the last HIP or internal error on this context ("" if none). */
+const char *pdd_last_error(const pdd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDD_H */

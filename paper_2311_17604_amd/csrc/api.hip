@@ -1,0 +1,216 @@
+// C ABI of libpdd: argument checks, context, scratch pool and entry points.
+#include <new>
+#include <string>
+
+#include "common.h"
+
+namespace pdd {
+
+int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, int64_t keep, int32_t* kept,
+             int32_t* order, uint64_t* order_cost);
+
+int hip_fail(Ctx* c, hipError_t e, const char* what) {
+    if (c) c->err = std::string(what) + ": " + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory) return PDD_ENOMEM;
+    return PDD_EHIP;
+}
+
+void* scratch(Ctx* c, int slot, size_t bytes) {
+    if (slot < 0 || slot >= 96) return nullptr;
+    Ctx::Buf& b = c->bufs[slot];
+    if (b.bytes >= bytes && b.p) return b.p;
+    if (b.p) {
+        // work already queued may still use the old buffer
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return nullptr;
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = bytes < 256 ? 256 : bytes;
+    want = (want + 255) & ~(size_t)255;
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        c->err = "hipMalloc of scratch failed (" + std::to_string(want) + " bytes)";
+        return nullptr;
+    }
+    b.bytes = want;
+    return b.p;
+}
+
+// Buffer width of the neighbour lists: k + b rounded up to a compiled size.
+static int list_width(int kb) {
+    if (kb <= 8) return 8;
+    if (kb <= 16) return 16;
+    if (kb <= 24) return 24;
+    return 32;
+}
+
+}  // namespace pdd
+
+struct pdd_ctx {
+    pdd::Ctx c;
+};
+
+struct pdd_grid {
+    pdd::Grid g;
+};
+
+using pdd::Ctx;
+
+extern "C" {
+
+const char* pdd_strerror(int status) {
+    switch (status) {
+        case PDD_OK: return "ok";
+        case PDD_EINVAL: return "invalid argument";
+        case PDD_ERANGE: return "coordinate extent too large (>= 2^21 mm on an axis)";
+        case PDD_ENOMEM: return "out of device memory";
+        case PDD_EHIP: return "HIP runtime error";
+        case PDD_EINTERNAL: return "internal error";
+        default: return "unknown status";
+    }
+}
+
+const char* pdd_last_error(const pdd_ctx* ctx) { return ctx ? ctx->c.err.c_str() : ""; }
+
+int pdd_ctx_create(pdd_ctx** out, int hip_device, void* hip_stream) {
+    if (!out) return PDD_EINVAL;
+    *out = nullptr;
+    pdd_ctx* x = new (std::nothrow) pdd_ctx();
+    if (!x) return PDD_ENOMEM;
+    Ctx* c = &x->c;
+    c->device = hip_device;
+    c->stream = (hipStream_t)hip_stream;
+    hipError_t e = hipSetDevice(hip_device);
+    if (e == hipSuccess) e = hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete x;
+        return PDD_EHIP;
+    }
+    *out = x;
+    return PDD_OK;
+}
+
+void pdd_ctx_destroy(pdd_ctx* ctx) {
+    if (!ctx) return;
+    Ctx* c = &ctx->c;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& b : c->bufs)
+        if (b.p) (void)hipFree(b.p);
+    for (auto& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    delete ctx;
+}
+
+int pdd_build_grid(pdd_ctx* ctx, const int32_t* d_xyz, int64_t n, int32_t stride, int32_t voxel_log2,
+                   pdd_grid** out) {
+    if (!ctx || !d_xyz || !out || n < 2 || (stride != 12 && stride != 16)) return PDD_EINVAL;
+    *out = nullptr;
+    Ctx* c = &ctx->c;
+    if (hipSetDevice(c->device) != hipSuccess) return PDD_EHIP;
+    pdd_grid* g = new (std::nothrow) pdd_grid();
+    if (!g) return PDD_ENOMEM;
+    int rc = pdd::build_grid(c, d_xyz, n, stride, voxel_log2, &g->g);
+    if (rc) {
+        (void)hipStreamSynchronize(c->stream);
+        pdd::free_grid(&g->g);
+        delete g;
+        return rc;
+    }
+    *out = g;
+    return PDD_OK;
+}
+
+void pdd_grid_free(pdd_ctx* ctx, pdd_grid* grid) {
+    if (!grid) return;
+    if (ctx) {
+        (void)hipSetDevice(ctx->c.device);
+        (void)hipStreamSynchronize(ctx->c.stream);
+    }
+    pdd::free_grid(&grid->g);
+    delete grid;
+}
+
+int pdd_grid_info(const pdd_grid* grid, int64_t* ncells, int32_t* voxel_log2) {
+    if (!grid) return PDD_EINVAL;
+    if (ncells) *ncells = grid->g.v.lv[0].ncells;
+    if (voxel_log2) *voxel_log2 = grid->g.v.lv[0].s;
+    return PDD_OK;
+}
+
+int pdd_knn_cost(pdd_ctx* ctx, const pdd_grid* grid, int32_t k, int32_t b, int32_t* d_nbr, int64_t* d_r2k,
+                 uint64_t* d_cost) {
+    if (!ctx || !grid || !d_cost || k < 1 || b < 0 || k + b > pdd::kMaxK) return PDD_EINVAL;
+    Ctx* c = &ctx->c;
+    if (hipSetDevice(c->device) != hipSuccess) return PDD_EHIP;
+    const pdd::GridView& g = grid->g.v;
+    const int K = pdd::list_width(k + b);
+    pdd::KnnOut ko;
+    ko.nbr = (int32_t*)pdd::scratch(c, 56, (size_t)g.n * K * 4);
+    ko.cnt = (uint8_t*)pdd::scratch(c, 57, (size_t)g.n);
+    ko.cost = (uint64_t*)pdd::scratch(c, 58, (size_t)g.n * 8);
+    ko.r2k = (int64_t*)pdd::scratch(c, 59, (size_t)g.n * 8);
+    if (!ko.nbr || !ko.cnt || !ko.cost || !ko.r2k) return PDD_ENOMEM;
+    int rc = pdd::knn_all(c, g, k, K, ko, nullptr);
+    if (rc) return rc;
+    return pdd::knn_to_original(c, g, K, k + b, ko, d_nbr, d_r2k, d_cost);
+}
+
+int pdd_decimate(pdd_ctx* ctx, const int32_t* d_xyz, int64_t n, int64_t keep_count, const pdd_opts* opts,
+                 int32_t* d_kept, int32_t* d_order, uint64_t* d_order_cost) {
+    if (!ctx || !d_xyz || !opts || !d_kept || n < 2 || n >= (int64_t)0x7FFFFFFF) return PDD_EINVAL;
+    if (keep_count < 1 || keep_count > n) return PDD_EINVAL;
+    const int k = opts->k;
+    if (k < 1 || k > pdd::kMaxK) return PDD_EINVAL;
+    int b = opts->b;
+    if (b < 0) return PDD_EINVAL;
+    if (b == 0) b = (pdd::kMaxK - k) < 8 ? (pdd::kMaxK - k) : 8;
+    if (k + b > pdd::kMaxK) return PDD_EINVAL;
+    float frac = opts->round_frac == 0.0f ? 0.03f : opts->round_frac;
+    if (!(frac > 0.0f && frac <= 1.0f)) return PDD_EINVAL;
+    const int stride = opts->point_stride == 0 ? 12 : opts->point_stride;
+    if (stride != 12 && stride != 16) return PDD_EINVAL;
+    if (opts->voxel_log2 != 0 && (opts->voxel_log2 < 2 || opts->voxel_log2 > 20)) return PDD_EINVAL;
+    Ctx* c = &ctx->c;
+    if (hipSetDevice(c->device) != hipSuccess) return PDD_EHIP;
+    for (auto& s : c->stats) s = 0;
+    for (auto& t : c->phase_ms) t = 0.0f;
+    c->timing = (opts->flags & PDD_F_TIMING) != 0;
+    if (c->timing && !c->ev[0])
+        for (auto& e : c->ev)
+            if (hipEventCreate(&e) != hipSuccess) return PDD_EHIP;
+    pdd::mark(c, pdd::kPhStart);
+    pdd::Grid grid;
+    int rc = pdd::build_grid(c, d_xyz, n, stride, opts->voxel_log2, &grid);
+    if (rc == PDD_OK) {
+        const int K = pdd::list_width(k + b);
+        c->stats[5] = grid.v.lv[0].s;
+        c->stats[6] = K;
+        rc = pdd::decimate(c, grid, k, K, frac, (opts->flags & PDD_F_CHECK) ? 1 : 0, keep_count, d_kept, d_order,
+                           d_order_cost);
+    }
+    (void)hipStreamSynchronize(c->stream);
+    if (rc == PDD_OK && c->timing)
+        for (int i = 1; i < pdd::kPhCount; i++) (void)hipEventElapsedTime(&c->phase_ms[i - 1], c->ev[i - 1], c->ev[i]);
+    pdd::free_grid(&grid);
+    return rc;
+}
+
+int pdd_last_stats(const pdd_ctx* ctx, int64_t* stats, int n) {
+    if (!ctx || !stats || n < 0) return 0;
+    int m = n < 8 ? n : 8;
+    for (int i = 0; i < m; i++) stats[i] = ctx->c.stats[i];
+    return m;
+}
+
+int pdd_last_timing(const pdd_ctx* ctx, float* ms, int n) {
+    if (!ctx || !ms || n < 0) return 0;
+    int m = n < pdd::kPhCount - 1 ? n : pdd::kPhCount - 1;
+    for (int i = 0; i < m; i++) ms[i] = ctx->c.phase_ms[i];
+    return m;
+}
+
+}  // extern "C"

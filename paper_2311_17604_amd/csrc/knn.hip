@@ -1,0 +1,76 @@
+// Initial k-nearest-neighbour lists and costs of every point (Eq. 11).
+#include "search.h"
+
+namespace pdd {
+
+namespace {
+
+// One lane per query in Morton order, so the lanes of a wave share cells.
+template <int K>
+__global__ void __launch_bounds__(kBlock) knn_all_k(GridView g, int k, int32_t* __restrict__ nbr,
+                                                    uint8_t* __restrict__ cnt, uint64_t* __restrict__ cost,
+                                                    int64_t* __restrict__ r2k) {
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= g.n) return;
+    const int4 qp = g.pts[q];
+    TopK<K> t;
+    t.init();
+    SearchCtx sc{nullptr, nullptr, 0};
+    ring_search<K, kAll>(g, q, qp, sc, t, K);
+    const int c = t.count();
+    const int use = c < k ? c : k;
+#pragma unroll
+    for (int j = 0; j < K; j++) nbr[(size_t)q * K + j] = t.id[j];
+    cnt[q] = (uint8_t)c;
+    cost[q] = list_cost<K>(t, use);
+    if (r2k) {
+        uint64_t r = 0;
+#pragma unroll
+        for (int j = 0; j < K; j++)
+            if (j == use - 1) r = t.d[j];
+        r2k[q] = (int64_t)r;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) to_original_k(const int4* __restrict__ pts, uint32_t n, int K, int Kout,
+                                                        const int32_t* __restrict__ nbr_s,
+                                                        const uint64_t* __restrict__ cost_s,
+                                                        const int64_t* __restrict__ r2k_s, int32_t* __restrict__ nbr,
+                                                        int64_t* __restrict__ r2k, uint64_t* __restrict__ cost) {
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const uint32_t o = (uint32_t)pts[q].w;
+    if (nbr)
+        for (int j = 0; j < Kout; j++) {
+            int32_t id = nbr_s[(size_t)q * K + j];
+            nbr[(size_t)o * Kout + j] = id >= 0 ? pts[id].w : -1;
+        }
+    if (r2k) r2k[o] = r2k_s[q];
+    cost[o] = cost_s[q];
+}
+
+}  // namespace
+
+int knn_all(Ctx* c, const GridView& g, int k, int K, KnnOut out, int64_t* fallbacks) {
+    if (fallbacks) *fallbacks = 0;
+    dim3 grid((g.n + kBlock - 1) / kBlock), block(kBlock);
+    switch (K) {
+        case 8: hipLaunchKernelGGL(knn_all_k<8>, grid, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
+        case 16: hipLaunchKernelGGL(knn_all_k<16>, grid, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
+        case 24: hipLaunchKernelGGL(knn_all_k<24>, grid, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
+        case 32: hipLaunchKernelGGL(knn_all_k<32>, grid, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
+        default: return PDD_EINVAL;
+    }
+    PDD_HIP(c, hipGetLastError());
+    return PDD_OK;
+}
+
+int knn_to_original(Ctx* c, const GridView& g, int K, int Kout, const KnnOut& in, int32_t* nbr, int64_t* r2k,
+                    uint64_t* cost) {
+    hipLaunchKernelGGL(to_original_k, dim3((g.n + kBlock - 1) / kBlock), dim3(kBlock), 0, c->stream, g.pts, g.n, K,
+                       Kout, in.nbr, in.cost, in.r2k, nbr, r2k, cost);
+    PDD_HIP(c, hipGetLastError());
+    return PDD_OK;
+}
+
+}  // namespace pdd

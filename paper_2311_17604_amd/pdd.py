@@ -1,0 +1,177 @@
+"""Thin ctypes binding of libpdd (the C ABI in include/pdd.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch provides device memory and the stream.  The library must have been
+built (``paper_2311_17604_amd.build``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdd.so")
+
+PDD_OK, PDD_EINVAL, PDD_ERANGE, PDD_ENOMEM, PDD_EHIP, PDD_EINTERNAL = range(6)
+PDD_F_CHECK = 1
+PDD_F_TIMING = 2
+PHASES = ("grid", "knn", "reverse", "rounds", "final")
+
+STATS = ("rounds", "researches", "rho_searches", "reverse_rebuilds", "knn_fallbacks", "voxel_log2",
+         "list_width", "touched")
+
+_lib = None
+
+
+class PddError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("b", ctypes.c_int32), ("voxel_log2", ctypes.c_int32),
+                ("round_frac", ctypes.c_float), ("point_stride", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+def load():
+    """Load libpdd.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libpdd.so is not built (run paper_2311_17604_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.pdd_ctx_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, P]
+    lib.pdd_ctx_create.restype = ctypes.c_int
+    lib.pdd_ctx_destroy.argtypes = [P]
+    lib.pdd_ctx_destroy.restype = None
+    lib.pdd_build_grid.argtypes = [P, P, i64, i32, i32, ctypes.POINTER(P)]
+    lib.pdd_build_grid.restype = ctypes.c_int
+    lib.pdd_grid_free.argtypes = [P, P]
+    lib.pdd_grid_free.restype = None
+    lib.pdd_grid_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    lib.pdd_grid_info.restype = ctypes.c_int
+    lib.pdd_knn_cost.argtypes = [P, P, i32, i32, P, P, P]
+    lib.pdd_knn_cost.restype = ctypes.c_int
+    lib.pdd_decimate.argtypes = [P, P, i64, i64, ctypes.POINTER(Opts), P, P, P]
+    lib.pdd_decimate.restype = ctypes.c_int
+    lib.pdd_last_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.c_int]
+    lib.pdd_last_stats.restype = ctypes.c_int
+    lib.pdd_last_timing.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
+    lib.pdd_last_timing.restype = ctypes.c_int
+    lib.pdd_strerror.argtypes = [ctypes.c_int]
+    lib.pdd_strerror.restype = ctypes.c_char_p
+    lib.pdd_last_error.argtypes = [P]
+    lib.pdd_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Context:
+    """A libpdd context bound to one device and stream (torch's current
+    stream of that device by default)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = load()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = self.lib.pdd_ctx_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if rc != PDD_OK:
+            raise PddError(rc, "pdd_ctx_create: " + self.lib.pdd_strerror(rc).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pdd_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != PDD_OK:
+            detail = self.lib.pdd_last_error(self.h).decode()
+            raise PddError(rc, "%s: %s %s" % (what, self.lib.pdd_strerror(rc).decode(), detail))
+
+    def timing(self) -> dict:
+        """Phase durations (ms, HIP events) of the last timed decimation."""
+        arr = (ctypes.c_float * 8)()
+        n = self.lib.pdd_last_timing(self.h, arr, 8)
+        return {PHASES[i]: float(arr[i]) for i in range(n)}
+
+    def stats(self) -> dict:
+        arr = (ctypes.c_int64 * 8)()
+        n = self.lib.pdd_last_stats(self.h, arr, 8)
+        return {STATS[i]: int(arr[i]) for i in range(n)}
+
+
+def _points(xyz):
+    import torch
+    if not (isinstance(xyz, torch.Tensor) and xyz.is_cuda and xyz.dtype == torch.int32 and xyz.dim() == 2
+            and xyz.shape[1] in (3, 4) and xyz.is_contiguous()):
+        raise ValueError("points must be a contiguous int32 CUDA tensor of shape [n, 3] or [n, 4]")
+    return xyz, 4 * xyz.shape[1]
+
+
+def knn_cost(ctx: Context, xyz, k: int, b: int = 0, voxel_log2: int = 0):
+    """(nbr [n, k+b] int32, r2k [n] int64, cost [n] int64 holding uint64 bits)."""
+    import torch
+    pts, stride = _points(xyz)
+    n = pts.shape[0]
+    g = ctypes.c_void_p()
+    ctx._check(ctx.lib.pdd_build_grid(ctx.h, _ptr(pts), n, stride, voxel_log2, ctypes.byref(g)), "pdd_build_grid")
+    try:
+        nbr = torch.empty((n, k + b), dtype=torch.int32, device=pts.device)
+        r2k = torch.empty(n, dtype=torch.int64, device=pts.device)
+        cost = torch.empty(n, dtype=torch.int64, device=pts.device)
+        ctx._check(ctx.lib.pdd_knn_cost(ctx.h, g, k, b, _ptr(nbr), _ptr(r2k), _ptr(cost)), "pdd_knn_cost")
+        ctx.stream.synchronize()
+    finally:
+        ctx.lib.pdd_grid_free(ctx.h, g)
+    return nbr, r2k, cost
+
+
+def grid_info(ctx: Context, xyz, voxel_log2: int = 0):
+    pts, stride = _points(xyz)
+    g = ctypes.c_void_p()
+    ctx._check(ctx.lib.pdd_build_grid(ctx.h, _ptr(pts), pts.shape[0], stride, voxel_log2, ctypes.byref(g)),
+               "pdd_build_grid")
+    nc, s = ctypes.c_int64(), ctypes.c_int32()
+    ctx.lib.pdd_grid_info(g, ctypes.byref(nc), ctypes.byref(s))
+    ctx.lib.pdd_grid_free(ctx.h, g)
+    return int(nc.value), int(s.value)
+
+
+def decimate(ctx: Context, xyz, keep: int, k: int, b: int = 0, voxel_log2: int = 0, round_frac: float = 0.0,
+             check: bool = False, with_order: bool = True, out=None, timing: bool = False):
+    """Greedy decimation to `keep` points.  Returns (kept [keep] int32,
+    order [n-keep] int32 or None, order_cost [n-keep] int64 (uint64 bits) or
+    None).  `out` may supply preallocated (kept, order, order_cost)."""
+    import torch
+    pts, stride = _points(xyz)
+    n = pts.shape[0]
+    if out is not None:
+        kept, order, order_cost = out
+    else:
+        kept = torch.empty(keep, dtype=torch.int32, device=pts.device)
+        order = torch.empty(n - keep, dtype=torch.int32, device=pts.device) if with_order else None
+        order_cost = torch.empty(n - keep, dtype=torch.int64, device=pts.device) if with_order else None
+    o = Opts(k=k, b=b, voxel_log2=voxel_log2, round_frac=round_frac, point_stride=stride,
+             flags=(PDD_F_CHECK if check else 0) | (PDD_F_TIMING if timing else 0))
+    ctx._check(ctx.lib.pdd_decimate(ctx.h, _ptr(pts), n, keep, ctypes.byref(o), _ptr(kept), _ptr(order),
+                                    _ptr(order_cost)), "pdd_decimate")
+    return kept, order, order_cost

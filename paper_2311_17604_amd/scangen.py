@@ -90,51 +90,82 @@ def wall_scene(rng: np.random.Generator, nboxes: int, rmin_m: float, rmax_m: flo
     return Scene(lo, hi, close_lo, close_hi)
 
 
-def _cast(origin: np.ndarray, d: np.ndarray, scene: Scene) -> np.ndarray:
-    """Range (mm) to the first hit of rays origin + t d (d unit, [m, 3])."""
+def _slab(o, lo, hi, dx, dy, dz):
+    """Entry distance of rays o + t (dx, dy, dz) into the box [lo, hi]
+    (inf where the ray misses it or starts past it)."""
     with np.errstate(divide="ignore", invalid="ignore"):
-        inv = 1.0 / d
-        # exit distance from the closing box (origin is inside it)
-        t1 = (scene.close_lo[None, :] - origin[None, :]) * inv
-        t2 = (scene.close_hi[None, :] - origin[None, :]) * inv
-        tfar = np.where(np.isnan(np.maximum(t1, t2)), np.inf, np.maximum(t1, t2))
-        best = tfar.min(axis=1)
-        for b in range(scene.box_lo.shape[0]):
-            a1 = (scene.box_lo[b][None, :] - origin[None, :]) * inv
-            a2 = (scene.box_hi[b][None, :] - origin[None, :]) * inv
-            tmin = np.minimum(a1, a2)
-            tmax = np.maximum(a1, a2)
-            tmin = np.where(np.isnan(tmin), -np.inf, tmin)
-            tmax = np.where(np.isnan(tmax), np.inf, tmax)
-            tn = tmin.max(axis=1)
-            tf = tmax.min(axis=1)
-            hit = (tn <= tf) & (tn > 0.0)
-            best = np.where(hit & (tn < best), tn, best)
-    return best
+        tn = np.full(dx.shape, -np.inf)
+        tf = np.full(dx.shape, np.inf)
+        for a, d in enumerate((dx, dy, dz)):
+            inv = 1.0 / d
+            t1 = (lo[a] - o[a]) * inv
+            t2 = (hi[a] - o[a]) * inv
+            a_min = np.where(np.isnan(t1), -np.inf, np.minimum(t1, t2))
+            a_max = np.where(np.isnan(t1), np.inf, np.maximum(t1, t2))
+            tn = np.maximum(tn, a_min)
+            tf = np.minimum(tf, a_max)
+        return np.where((tn <= tf) & (tn > 0.0), tn, np.inf)
+
+
+def _exit(o, lo, hi, dx, dy, dz):
+    """Exit distance of rays starting inside the box [lo, hi]."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t = np.full(dx.shape, np.inf)
+        for a, d in enumerate((dx, dy, dz)):
+            bound = np.where(d > 0, hi[a], lo[a])
+            ta = (bound - o[a]) / d
+            t = np.minimum(t, np.where(d == 0, np.inf, ta))
+        return t
+
+
+def _window(o, lo, hi, rows, cols):
+    """Row range and column indices of the rays that can reach box [lo, hi]
+    from station o (conservative: footprint corners bound the azimuth; the
+    nearest and farthest horizontal distances bound the elevation)."""
+    cx = np.array([lo[0], hi[0], lo[0], hi[0]]) - o[0]
+    cy = np.array([lo[1], lo[1], hi[1], hi[1]]) - o[1]
+    mid = math.atan2((lo[1] + hi[1]) / 2 - o[1], (lo[0] + hi[0]) / 2 - o[0])
+    diff = (np.arctan2(cy, cx) - mid + math.pi) % (2 * math.pi) - math.pi
+    a0, a1 = mid + diff.min(), mid + diff.max()
+    step = 2 * math.pi / cols
+    j0 = int(math.floor((a0 % (2 * math.pi)) / step)) - 1
+    nj = int(math.ceil((a1 - a0) / step)) + 3
+    jcols = np.arange(j0, j0 + min(nj, cols)) % cols
+    hx = max(lo[0] - o[0], 0.0, o[0] - hi[0])
+    hy = max(lo[1] - o[1], 0.0, o[1] - hi[1])
+    dmin = max(math.hypot(hx, hy), 1e-9)
+    dmax = float(np.sqrt(cx ** 2 + cy ** 2).max())
+    el_hi = math.atan2(hi[2] - o[2], dmin if hi[2] > o[2] else dmax)
+    el_lo = math.atan2(lo[2] - o[2], dmin if lo[2] < o[2] else dmax)
+    to_row = lambda e: (math.degrees(e) + 60.0) / 150.0 * (rows - 1)  # noqa: E731
+    i0 = max(0, int(math.floor(to_row(el_lo))) - 1)
+    i1 = min(rows, int(math.ceil(to_row(el_hi))) + 2)
+    return i0, i1, jcols
 
 
 def scan_station(rows: int, cols: int, station_xy_mm: tuple[float, float], scene: Scene,
-                 rng: np.random.Generator, sigma_mm: float = 2.0, height_mm: float = 1500.0,
-                 chunk_rows: int | None = None) -> np.ndarray:
+                 rng: np.random.Generator, sigma_mm: float = 2.0, height_mm: float = 1500.0) -> np.ndarray:
     """One station's R x C scan as int32 [R*C, 3], row-major (row, column)."""
     el, az = _ray_dirs(rows, cols)
-    origin = np.array([station_xy_mm[0], station_xy_mm[1], height_mm], dtype=np.float64)
-    cos_az, sin_az = np.cos(az), np.sin(az)
-    out = np.empty((rows * cols, 3), dtype=np.int32)
-    if chunk_rows is None:
-        chunk_rows = max(1, (1 << 20) // cols)
-    for r0 in range(0, rows, chunk_rows):
-        r1 = min(rows, r0 + chunk_rows)
-        ce = np.cos(el[r0:r1])[:, None]
-        se = np.sin(el[r0:r1])[:, None]
-        d = np.stack([np.broadcast_to(ce * cos_az[None, :], (r1 - r0, cols)),
-                      np.broadcast_to(ce * sin_az[None, :], (r1 - r0, cols)),
-                      np.broadcast_to(se, (r1 - r0, cols))], axis=-1).reshape(-1, 3)
-        t = _cast(origin, d, scene)
-        t = t + rng.normal(0.0, sigma_mm, size=t.shape[0])
-        p = origin[None, :] + t[:, None] * d
-        out[r0 * cols:r1 * cols] = np.rint(p).astype(np.int32)
-    return out
+    o = np.array([station_xy_mm[0], station_xy_mm[1], height_mm], dtype=np.float64)
+    ce, se = np.cos(el)[:, None], np.sin(el)[:, None]
+    ca, sa = np.cos(az)[None, :], np.sin(az)[None, :]
+    dx, dy, dz = ce * ca, ce * sa, np.broadcast_to(se, (rows, cols))
+    t = _exit(o, scene.close_lo, scene.close_hi, dx, dy, dz)
+    for b in range(scene.box_lo.shape[0]):
+        lo, hi = scene.box_lo[b], scene.box_hi[b]
+        i0, i1, jc = _window(o, lo, hi, rows, cols)
+        if i0 >= i1:
+            continue
+        sub = np.ix_(np.arange(i0, i1), jc)
+        tb = _slab(o, lo, hi, dx[sub], dy[sub], dz[sub])
+        t[sub] = np.minimum(t[sub], tb)
+    t = t + rng.normal(0.0, sigma_mm, size=t.shape)
+    out = np.empty((rows, cols, 3), dtype=np.int32)
+    out[..., 0] = np.rint(o[0] + t * dx)
+    out[..., 1] = np.rint(o[1] + t * dy)
+    out[..., 2] = np.rint(o[2] + t * dz)
+    return out.reshape(-1, 3)
 
 
 # ----------------------------------------------------------------------------
