@@ -27,6 +27,7 @@ def main():
     ap.add_argument("--voxel-log2", type=int, default=0)
     ap.add_argument("--b", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true", help="no per-50-round progress lines from the library")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding).",
@@ -47,7 +48,8 @@ def main():
     kept = torch.empty(w.keep, dtype=torch.int32, device="cuda")
     order = torch.empty(n - w.keep, dtype=torch.int32, device="cuda")
     oc = torch.empty(n - w.keep, dtype=torch.int64, device="cuda")
-    kw = dict(b=args.b, voxel_log2=args.voxel_log2, round_frac=args.round_frac, out=(kept, order, oc), timing=True)
+    kw = dict(b=args.b, voxel_log2=args.voxel_log2, round_frac=args.round_frac, out=(kept, order, oc), timing=True,
+              progress=not args.quiet)
     for i in range(args.warmup):
         pdd.decimate(ctx, x, w.keep, w.k, **kw)
         print("warmup %d done" % i, file=sys.stderr, flush=True)

@@ -68,6 +68,7 @@ typedef struct {
 
 #define PDD_F_CHECK 1       /* extra device-side invariant checks (slower) */
 #define PDD_F_TIMING 2      /* record HIP events per phase (see pdd_last_timing) */
+#define PDD_F_PROGRESS 4    /* print a progress line to stderr every 50 removal rounds */
 
 /* Create a context on HIP device `hip_device` that enqueues its work on
  * `hip_stream` (a hipStream_t; NULL = the null stream).  *out receives the

@@ -179,6 +179,7 @@ int pdd_decimate(pdd_ctx* ctx, const int32_t* d_xyz, int64_t n, int64_t keep_cou
     for (auto& s : c->stats) s = 0;
     for (auto& t : c->phase_ms) t = 0.0f;
     c->timing = (opts->flags & PDD_F_TIMING) != 0;
+    c->progress = (opts->flags & PDD_F_PROGRESS) != 0;
     if (c->timing && !c->ev[0])
         for (auto& e : c->ev)
             if (hipEventCreate(&e) != hipSuccess) return PDD_EHIP;

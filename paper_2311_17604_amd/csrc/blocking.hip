@@ -1,0 +1,412 @@
+// Which points of A are removed this round (the conditions are stated at the
+// top of rounds.hip).  All kernels here give one wavefront to one point.
+#include "rounds.h"
+
+namespace pdd {
+
+namespace {
+
+// y in A: its list entries, one per lane (lane j < K holds entry j).
+//  - blocks y when an entry of H(y) is nearer than rho'(y);
+//  - blocks every lower A entry x with fewer than k alive entries not in
+//    H(x) (other than x) within d(x, y) of y, or whose distance the list
+//    does not cover;
+//  - puts y on the danger list (with threshold key and list radius) when
+//    its list is full and holds fewer than k entries outside A.
+template <int K>
+__global__ void __launch_bounds__(kBlock) rb_pair(RoundArrays a) {
+    RoundDev* st = a.st;
+    if (st->done || st->err) return;
+    const uint32_t nA = st->nA, round = st->round;
+    const int k = a.k;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const uint32_t nw = gridDim.x * (kBlock / kWave);
+    for (uint32_t t = blockIdx.x * (kBlock / kWave) + w; t < nA; t += nw) {
+        const uint32_t y = a.A[t];
+        const int4 py = a.pts[y];
+        const uint64_t cy = a.cost[y];
+        const int32_t oy = py.w;
+        const int c = a.cnt[y];
+        int cls = 0;
+        uint64_t d = ~0ull, draw = 0, cj = 0;
+        int32_t oj = 0;
+        uint32_t z = 0;
+        if (lane < c) {
+            z = (uint32_t)a.nbr[(size_t)y * K + lane];
+            const int4 pz = a.pts[z];
+            draw = dist2(py.x, py.y, py.z, pz.x, pz.y, pz.z);
+            if (a.alive[z]) {
+                d = draw;
+                if (a.inA[z] == round) {
+                    cls = 2;
+                    cj = a.cost[z];
+                    oj = pz.w;
+                } else {
+                    cls = 1;
+                }
+            }
+        }
+        const uint64_t dlast = c > 0 ? readlane64(draw, c - 1) : 0ull;
+        const bool complete = c < K;
+        const bool higher = cls == 2 && key_above(cj, oj, cy, oy);
+        const bool low = cls != 0 && !higher;
+        const uint64_t lowm = __ballot(low), highm = __ballot(higher);
+        const uint64_t below_lane = (1ull << lane) - 1ull;
+        // y itself
+        bool blocked_self;
+        if (__popcll(lowm) >= k) {
+            const uint64_t km = __ballot(low && __popcll(lowm & below_lane) == k - 1);
+            const uint64_t rho = readlane64(d, __ffsll((unsigned long long)km) - 1);
+            blocked_self = highm && readlane64(d, __ffsll((unsigned long long)highm) - 1) < rho;
+        } else {
+            blocked_self = complete ? highm != 0 : true;
+        }
+        if (lane == 0 && blocked_self) a.blocked[y] = round;
+        // rank counts over the other entries (uniform loop, entries broadcast)
+        int q = 0, rankA = 0;
+        for (int i = 0; i < K; i++) {
+            const int ci = __builtin_amdgcn_readlane(cls, i);
+            if (ci == 0) continue;
+            const uint64_t di = readlane64(d, i);
+            const uint64_t ki = readlane64(cj, i);
+            const int32_t oi = __builtin_amdgcn_readlane(oj, i);
+            if (i != lane && di <= d && (ci == 1 || key_above(cj, oj, ki, oi))) q++;
+            if (ci == 2 && i != lane && key_above(cj, oj, ki, oi)) rankA++;
+        }
+        const bool lower = cls == 2 && !higher;
+        const bool covered = complete || d < dlast;
+        if (lower && (q < k || !covered)) a.blocked[z] = round;
+        // lower points beyond the list
+        const int nL = __popcll(__ballot(cls == 1)), nAe = __popcll(__ballot(cls == 2));
+        if (!complete && nL < k) {
+            const int need = k - nL;
+            uint64_t tc = cy;
+            int32_t to = oy;
+            if (nAe >= need) {
+                // the need-th lowest key among the alive A entries
+                const uint64_t m = __ballot(cls == 2 && rankA == need - 1);
+                const int l = __ffsll((unsigned long long)m) - 1;
+                tc = readlane64(cj, l);
+                to = __builtin_amdgcn_readlane(oj, l);
+            }
+            if (lane == 0) {
+                const uint32_t p = atomicAdd(&st->nDanger, 1u);
+                a.dg_y[p] = y;
+                a.dg_tc[p] = tc;
+                a.dg_to[p] = to;
+                a.dg_dlast[p] = dlast;
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) rb_survive(RoundArrays a) {
+    RoundDev* st = a.st;
+    if (st->done || st->err) return;
+    const uint32_t nA = st->nA, round = st->round;
+    const uint32_t n_it = (nA + blockDim.x - 1) / blockDim.x * blockDim.x;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_it; t += gridDim.x * blockDim.x) {
+        bool sv = false;
+        uint32_t x = 0;
+        uint64_t cmax = 0;
+        if (t < nA) {
+            x = a.A[t];
+            cmax = a.cost[x];
+            const int lev = level_of(st, cmax);
+            atomicAdd(&a.cellAlev[(size_t)a.cell_of[x] * kLev + lev], 1u);
+            atomicAdd(&a.ccellAlev[(size_t)a.coarse_of[x] * kLev + lev], 1u);
+            if (a.blocked[x] != round) {
+                sv = true;
+                a.surv[x] = round;
+                atomicAdd(&a.ccS[a.coarse_of[x]], 1u);
+            }
+        }
+        const uint32_t p = wave_append(&st->nSurv, sv);
+        if (sv) a.surv_list[p] = x;
+        // highest cost of A (wave maximum, one atomic per wave)
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)cmax, o, kWave);
+            const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(cmax >> 32), o, kWave);
+            const uint64_t v = ((uint64_t)hi << 32) | lo;
+            cmax = v > cmax ? v : cmax;
+        }
+        if ((threadIdx.x & (kWave - 1)) == 0 && cmax)
+            atomicMax((unsigned long long*)&st->top_cost, (unsigned long long)cmax);
+    }
+}
+
+// Groups the survivors by coarse cell (offsets from the scan of ccS); takes
+// ccS back to zero on the way.
+__global__ void __launch_bounds__(kBlock) rb_bucket(RoundArrays a) {
+    RoundDev* st = a.st;
+    if (st->done || st->err) return;
+    const uint32_t ns = st->nSurv;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ns; t += gridDim.x * blockDim.x) {
+        const uint32_t x = a.surv_list[t];
+        const uint32_t cc = a.coarse_of[x];
+        const uint32_t slot = a.surv_off[cc] + atomicSub(&a.ccS[cc], 1u) - 1u;
+        a.surv_bucket[slot] = x;
+        // the highest key survives every condition; find its index
+        if (a.cost[x] == st->top_cost) atomicMin(&st->top_orig, a.pts[x].w);
+    }
+}
+
+// For each key level j: the first Chebyshev ring r <= RMAX around cell
+// (cx, cy, cz) of a grid level whose block holds at least k alive points
+// ranked below level j (outside A, or in A at a lower level), from per-cell
+// counts; -1 if none.  *cover: the block of radius RMAX covers the grid.
+template <int RMAX>
+__device__ void ring_levels(const LevelView& lv, int cx, int cy, int cz, const uint32_t* alive_cnt,
+                            const uint32_t* alev, int k, int* rj, bool* cover) {
+    const int lane = (int)lane_id();
+    constexpr int side = 2 * RMAX + 1, ncube = side * side * side;
+    uint32_t acc[RMAX + 1][kLev];
+#pragma unroll
+    for (int r = 0; r <= RMAX; r++)
+#pragma unroll
+        for (int j = 0; j < kLev; j++) acc[r][j] = 0;
+    for (int base = 0; base < ncube; base += kWave) {
+        const int idx = base + lane;
+        if (idx < ncube) {
+            const int dz = idx / (side * side) - RMAX;
+            const int rem = idx % (side * side);
+            const int dy = rem / side - RMAX, dx = rem % side - RMAX;
+            const int x = cx + dx, y = cy + dy, z = cz + dz;
+            if (x >= 0 && y >= 0 && z >= 0 && x <= lv.cmax[0] && y <= lv.cmax[1] && z <= lv.cmax[2]) {
+                const uint32_t c =
+                    hash_find(lv.hkeys, lv.hvals, lv.hmask, morton3((uint32_t)x, (uint32_t)y, (uint32_t)z));
+                if (c != kNone) {
+                    const int ring = max(abs(dx), max(abs(dy), abs(dz)));
+                    uint32_t la[kLev], inA = 0;
+#pragma unroll
+                    for (int j = 0; j < kLev; j++) {
+                        la[j] = alev[(size_t)c * kLev + j];
+                        inA += la[j];
+                    }
+                    uint32_t below = alive_cnt[c] - inA;
+#pragma unroll
+                    for (int j = 0; j < kLev; j++) {
+#pragma unroll
+                        for (int r = 0; r <= RMAX; r++)
+                            if (ring <= r) acc[r][j] += below;
+                        below += la[j];
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kLev; j++) rj[j] = -1;
+#pragma unroll
+    for (int r = RMAX; r >= 0; r--)
+#pragma unroll
+        for (int j = 0; j < kLev; j++) {
+            uint32_t v = acc[r][j];
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, kWave);
+            if (v >= (uint32_t)k) rj[j] = r;
+        }
+    *cover = cx - RMAX <= 0 && cy - RMAX <= 0 && cz - RMAX <= 0 && cx + RMAX >= lv.cmax[0] &&
+             cy + RMAX >= lv.cmax[1] && cz + RMAX >= lv.cmax[2];
+}
+
+// A dangerous y may hold a surviving lower x beyond its list within
+// rho(x | y) only if key(x) <= its threshold.  For x of key level j,
+// rho(x | y) is below R_j, the radius of the smallest cell block around y
+// with k alive points ranked below level j.  Such an x stays unless a count
+// of alive points not above x within d(x, y) of y reaches k: the entries of
+// y's list not above x, plus entries of x's own list that lie beyond y's
+// list radius and within d(x, y).  When no R_j is found, every survivor of
+// level j at or below min(key(y), threshold) waits (cost bound in
+// glob_block, applied at removal).
+template <int K>
+__global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
+    RoundDev* st = a.st;
+    if (st->done || st->err || st->nSurv == 0) return;
+    constexpr int W = kBlock / kWave;
+    __shared__ uint32_t s_start[W][kWave], s_excl[W][kWave];
+    __shared__ uint64_t s_yc[W][K];
+    __shared__ int32_t s_yo[W][K];
+    __shared__ int s_ycls[W][K];
+    const uint32_t nd = st->nDanger, round = st->round, ns = st->nSurv;
+    const int k = a.k, Kb = a.K;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const uint32_t nw = gridDim.x * W;
+    for (uint32_t t = blockIdx.x * W + w; t < nd; t += nw) {
+        const uint32_t y = a.dg_y[t];
+        const uint64_t tc = a.dg_tc[t], dlast = a.dg_dlast[t];
+        const int32_t to = a.dg_to[t];
+        const int4 py = a.pts[y];
+        const uint64_t cy = a.cost[y];
+        const int32_t oy = py.w;
+        // y's list: class and key of every entry
+        if (lane < K) {
+            int cls = 0;
+            uint64_t cc = 0;
+            int32_t oo = 0;
+            if (lane < a.cnt[y]) {
+                const uint32_t z = (uint32_t)a.nbr[(size_t)y * Kb + lane];
+                if (a.alive[z]) {
+                    if (a.inA[z] == round) {
+                        cls = 2;
+                        cc = a.cost[z];
+                        oo = a.pts[z].w;
+                    } else {
+                        cls = 1;
+                    }
+                }
+            }
+            s_ycls[w][lane] = cls;
+            s_yc[w][lane] = cc;
+            s_yo[w][lane] = oo;
+        }
+        wave_sync_lds();
+        const int ux = py.x - g.minx, uy = py.y - g.miny, uz = py.z - g.minz;
+        // R2[j] (0 = none found) for the key levels up to the threshold's
+        const int lth = level_of(st, tc);
+        uint64_t R2[kLev];
+        uint64_t rbox = 0;
+        {
+            int r0[kLev], r1[kLev];
+            bool cover0, cover1;
+            const LevelView& l0 = g.lv[0];
+            ring_levels<2>(l0, ux >> l0.s, uy >> l0.s, uz >> l0.s, a.cell_alive, a.cellAlev, k, r0, &cover0);
+            bool need1 = false;
+#pragma unroll
+            for (int j = 0; j < kLev; j++) {
+                R2[j] = 0;
+                if (r0[j] >= 0) {
+                    const uint64_t e = (uint64_t)(r0[j] + 1) << l0.s;
+                    R2[j] = 3 * e * e;
+                } else if (j <= lth && !cover0) {
+                    need1 = true;
+                }
+            }
+            if (need1) {
+                const LevelView& l1 = g.lv[1];
+                ring_levels<6>(l1, ux >> l1.s, uy >> l1.s, uz >> l1.s, a.ccell_alive, a.ccellAlev, k, r1, &cover1);
+#pragma unroll
+                for (int j = 0; j < kLev; j++)
+                    if (R2[j] == 0 && r1[j] >= 0) {
+                        const uint64_t e = (uint64_t)(r1[j] + 1) << l1.s;
+                        R2[j] = 3 * e * e;
+                    }
+            }
+            const uint64_t cb = (cy < tc ? cy : tc) + 1;
+#pragma unroll
+            for (int j = 0; j < kLev; j++) {
+                if (j > lth) continue;
+                if (R2[j] == 0) {
+                    if (lane == 0) atomicMax((unsigned long long*)&st->glob_block[j], (unsigned long long)cb);
+                } else if (R2[j] > rbox) {
+                    rbox = R2[j];
+                }
+            }
+        }
+        auto consider = [&](uint32_t x) {
+            if (x == y || a.surv[x] != round) return;
+            const uint64_t cx = a.cost[x];
+            const int lx = level_of(st, cx);
+            if (lx > lth || R2[lx] == 0) return;  // above the threshold, or waiting on glob_block
+            const int4 px = a.pts[x];
+            const uint64_t dxy = dist2(px.x, px.y, px.z, py.x, py.y, py.z);
+            if (dxy < dlast || dxy >= R2[lx]) return;
+            const int32_t ox = px.w;
+            if (key_above(cx, ox, cy, oy) || key_above(cx, ox, tc, to)) return;
+            // witnesses not above x within d(x, y) of y
+            int q = 0;
+            for (int i = 0; i < K; i++) {
+                const int ci = s_ycls[w][i];
+                if (ci == 1 || (ci == 2 && key_above(cx, ox, s_yc[w][i], s_yo[w][i]))) q++;
+            }
+            const int cxn = a.cnt[x];
+            for (int j = 0; j < cxn && q < k; j++) {
+                const uint32_t z = (uint32_t)a.nbr[(size_t)x * Kb + j];
+                if (z == y || !a.alive[z]) continue;
+                const int4 pz = a.pts[z];
+                const uint64_t dyz = dist2(pz.x, pz.y, pz.z, py.x, py.y, py.z);
+                if (dyz <= dlast || dyz > dxy) continue;
+                if (a.inA[z] == round && key_above(a.cost[z], pz.w, cx, ox)) continue;
+                q++;
+            }
+            if (q < k) a.blocked[x] = round;
+        };
+        (void)ns;
+        if (rbox != 0) {
+            const LevelView& l1 = g.lv[1];
+            const int sc = l1.s;
+            const int ri = (int)sqrt((double)rbox) + 1;
+            const int x0 = max((ux - ri) >> sc, 0), x1 = min((ux + ri) >> sc, l1.cmax[0]);
+            const int y0 = max((uy - ri) >> sc, 0), y1 = min((uy + ri) >> sc, l1.cmax[1]);
+            const int z0 = max((uz - ri) >> sc, 0), z1 = min((uz + ri) >> sc, l1.cmax[2]);
+            const int nx = x1 - x0 + 1, nyy = y1 - y0 + 1, nz = z1 - z0 + 1;
+            const int nbox = nx * nyy * nz;
+            for (int base = 0; base < nbox; base += kWave) {
+                const int idx = base + lane;
+                uint32_t st0 = 0, cnt = 0;
+                if (idx < nbox) {
+                    const int xx = x0 + idx % nx, yy = y0 + (idx / nx) % nyy, zz = z0 + idx / (nx * nyy);
+                    const uint32_t c =
+                        hash_find(l1.hkeys, l1.hvals, l1.hmask, morton3((uint32_t)xx, (uint32_t)yy, (uint32_t)zz));
+                    if (c != kNone) {
+                        st0 = a.surv_off[c];
+                        cnt = a.surv_off[c + 1] - st0;
+                    }
+                }
+                uint32_t incl = cnt;
+#pragma unroll
+                for (int o = 1; o < kWave; o <<= 1) {
+                    const uint32_t v = (uint32_t)__shfl_up((int)incl, o, kWave);
+                    if (lane >= o) incl += v;
+                }
+                const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+                if (total == 0) continue;
+                s_start[w][lane] = st0;
+                s_excl[w][lane] = incl - cnt;
+                wave_sync_lds();
+                for (uint32_t t0 = 0; t0 < total; t0 += kWave) {
+                    const uint32_t u = t0 + (uint32_t)lane;
+                    if (u < total) {
+                        int l = 0;
+#pragma unroll
+                        for (int step = 32; step > 0; step >>= 1)
+                            if (s_excl[w][l + step] <= u) l += step;
+                        consider(a.surv_bucket[s_start[w][l] + (u - s_excl[w][l])]);
+                    }
+                }
+                wave_sync_lds();
+            }
+        }
+        wave_sync_lds();
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&st->stat_danger, nd);
+}
+
+template <int K>
+int launch_k(Ctx* c, const RoundArrays& a, const GridView& g) {
+    const unsigned G = 1024;
+    hipLaunchKernelGGL(rb_pair<K>, dim3(G), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(rb_survive, dim3(G), dim3(kBlock), 0, c->stream, a);
+    PDD_HIP(c, hipGetLastError());
+    int rc = exclusive_scan_u32(c, a.ccS, a.surv_off, a.nccells + 1, nullptr);
+    if (rc) return rc;
+    hipLaunchKernelGGL(rb_bucket, dim3(G), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(rb_danger<K>, dim3(G), dim3(kBlock), 0, c->stream, a, g);
+    PDD_HIP(c, hipGetLastError());
+    return PDD_OK;
+}
+
+}  // namespace
+
+int launch_blocking(Ctx* c, const RoundArrays& a, const GridView& g, int K) {
+    switch (K) {
+        case 8: return launch_k<8>(c, a, g);
+        case 16: return launch_k<16>(c, a, g);
+        case 24: return launch_k<24>(c, a, g);
+        case 32: return launch_k<32>(c, a, g);
+        default: return PDD_EINVAL;
+    }
+}
+
+}  // namespace pdd

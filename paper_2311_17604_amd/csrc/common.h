@@ -141,6 +141,7 @@ struct Ctx {
     void* pinned = nullptr;   // small pinned host buffer for status read-back
     // phase timing (PDD_F_TIMING): events recorded on the context's stream
     bool timing = false;
+    bool progress = false;    // PDD_F_PROGRESS: a line to stderr every 50 rounds
     hipEvent_t ev[8] = {};
     float phase_ms[8] = {0};
 };

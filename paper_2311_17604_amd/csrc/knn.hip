@@ -1,4 +1,8 @@
 // Initial k-nearest-neighbour lists and costs of every point (Eq. 11).
+#include <stdlib.h>
+
+#include <algorithm>
+
 #include "search.h"
 
 namespace pdd {
@@ -32,6 +36,32 @@ __global__ void __launch_bounds__(kBlock) knn_all_k(GridView g, int k, int32_t* 
     }
 }
 
+// One wavefront per query (see wave_knn).
+template <int K>
+__global__ void __launch_bounds__(kBlock) knn_wave_k(GridView g, int k, int32_t* __restrict__ nbr,
+                                                     uint8_t* __restrict__ cnt, uint64_t* __restrict__ cost,
+                                                     int64_t* __restrict__ r2k) {
+    __shared__ uint32_t lds[kBlock / kWave][2][kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const uint32_t nw = gridDim.x * (kBlock / kWave);
+    for (uint32_t q = blockIdx.x * (kBlock / kWave) + w; q < g.n; q += nw) {
+        const int4 qp = g.pts[q];
+        SearchCtx sc{nullptr, nullptr, 0};
+        uint64_t d;
+        int32_t id;
+        wave_knn<K, kAll>(g, q, qp, sc, K, d, id, lds[w][0], lds[w][1]);
+        const int c = __popcll(__ballot(lane < K && d != ~0ull));
+        const int use = c < k ? c : k;
+        const uint64_t wsum = wave_sum64(lane < use ? cost_term(d) : 0ull);
+        if (lane < K) nbr[(size_t)q * K + lane] = id;
+        if (lane == use - 1 && r2k) r2k[q] = (int64_t)d;
+        if (lane == 0) {
+            cnt[q] = (uint8_t)c;
+            cost[q] = wsum;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) to_original_k(const int4* __restrict__ pts, uint32_t n, int K, int Kout,
                                                         const int32_t* __restrict__ nbr_s,
                                                         const uint64_t* __restrict__ cost_s,
@@ -54,6 +84,19 @@ __global__ void __launch_bounds__(kBlock) to_original_k(const int4* __restrict__
 int knn_all(Ctx* c, const GridView& g, int k, int K, KnnOut out, int64_t* fallbacks) {
     if (fallbacks) *fallbacks = 0;
     dim3 grid((g.n + kBlock - 1) / kBlock), block(kBlock);
+    const char* mode = getenv("PDD_KNN_MODE");
+    if (!(mode && mode[0] == 'l')) {
+        dim3 wg(std::min<uint32_t>((g.n + 3) / 4, 65536u));
+        switch (K) {
+            case 8: hipLaunchKernelGGL(knn_wave_k<8>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
+            case 16: hipLaunchKernelGGL(knn_wave_k<16>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
+            case 24: hipLaunchKernelGGL(knn_wave_k<24>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
+            case 32: hipLaunchKernelGGL(knn_wave_k<32>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
+            default: return PDD_EINVAL;
+        }
+        PDD_HIP(c, hipGetLastError());
+        return PDD_OK;
+    }
     switch (K) {
         case 8: hipLaunchKernelGGL(knn_all_k<8>, grid, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
         case 16: hipLaunchKernelGGL(knn_all_k<16>, grid, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;

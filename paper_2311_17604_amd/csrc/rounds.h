@@ -1,0 +1,103 @@
+// Device state of the removal rounds, shared by rounds.hip and blocking.hip.
+#pragma once
+
+#include "search.h"
+
+namespace pdd {
+
+// A is split into kLev key levels per round (equal shares of A by
+// first-level bucket); points of a lower level rank below every point of a
+// higher one.
+constexpr int kLev = 4;
+
+struct RoundDev {
+    uint32_t n_alive, n_alive_new, removed, target, m, round, done, err;
+    uint32_t nA, nCand, nDanger, nSurv, nTouch, nResearch, nR, mode;
+    uint32_t sel_need, sel_bin, pad0, pad1;
+    int32_t sel_rem;  // key bits below the first-level prefix
+    uint32_t pool_count, pool_cap, overflow;
+    uint32_t stat_research, stat_danger, stat_touch, stat_surv;
+    uint32_t lev_t[kLev];         // level(x) = #{j >= 1 : bin0(cost x) >= lev_t[j]}
+    uint64_t glob_block[kLev];    // survivors of level j with cost < this wait
+    uint64_t top_cost;            // the round's highest key (never waits)
+    int32_t top_orig, pad2;
+    float frac;                   // share of alive points ranked this round (adapted)
+    float frac_max;
+};
+
+struct RoundArrays {
+    const int4* pts;
+    const uint32_t* cell_of;
+    const uint32_t* coarse_of;
+    uint8_t* alive;
+    uint64_t* cost;
+    int32_t* nbr;       // [n*K]
+    uint8_t* cnt;       // [n]
+    uint32_t* inA;      // round stamps
+    uint32_t* blocked;
+    uint32_t* touched;
+    uint32_t* surv;
+    uint32_t* alive_list[2];
+    uint32_t* A;
+    uint32_t* cand[2];
+    uint32_t* dg_y;      // danger list
+    uint64_t* dg_tc;
+    int32_t* dg_to;
+    uint64_t* dg_dlast;
+    uint32_t* touch_list;
+    uint32_t* research_list;
+    uint32_t* R;
+    uint64_t* ev_cost;
+    int32_t* ev_orig;
+    uint32_t* hist;      // [kSelBins0]
+    uint32_t* rev_off;   // [n+1]
+    int32_t* rev_src;    // [n*K]
+    int32_t* head;       // [n] pool chains
+    int32_t* pool_src;
+    int32_t* pool_next;
+    uint32_t* cell_alive;   // [ncells]
+    uint32_t* cellAlev;     // [ncells * kLev] A points per cell and level, this round
+    uint32_t* ccell_alive;  // [nccells]
+    uint32_t* ccellAlev;    // [nccells * kLev]
+    uint32_t* ccS;          // [nccells + 1] survivors per coarse cell, this round
+    uint32_t* surv_off;     // [nccells + 1] exclusive scan of ccS
+    uint32_t* surv_list;    // [n] survivors of this round
+    uint32_t* surv_bucket;  // [n] survivors grouped by coarse cell
+    RoundDev* st;
+    int k, K;
+    float frac;
+    int check;
+    uint32_t nccells;
+};
+
+__device__ inline uint32_t wave_append(uint32_t* counter, bool pred) {
+    const uint64_t m = __ballot(pred);
+    const uint32_t lane = lane_id();
+    const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+    uint32_t base = 0;
+    if (m && lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+    base = __shfl(base, (int)leader, kWave);
+    return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
+// First-level bucket of a cost: 0 for 0, else (msb + 1) * 64 + next 6 bits.
+// Monotone in the cost.
+__device__ inline uint32_t bin0(uint64_t c) {
+    if (c == 0) return 0;
+    const int e = 63 - __clzll(c);
+    const uint32_t mant = e >= 6 ? (uint32_t)(c >> (e - 6)) & 63u : (uint32_t)(c << (6 - e)) & 63u;
+    return (uint32_t)(e + 1) * 64u + mant;
+}
+
+__device__ inline int level_of(const RoundDev* st, uint64_t cost) {
+    const uint32_t b = bin0(cost);
+    int l = 0;
+#pragma unroll
+    for (int j = 1; j < kLev; j++) l += b >= st->lev_t[j];
+    return l;
+}
+
+// blocking kernels (blocking.hip), enqueued on the context's stream
+int launch_blocking(Ctx* c, const RoundArrays& a, const GridView& g, int K);
+
+}  // namespace pdd

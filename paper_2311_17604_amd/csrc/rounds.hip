@@ -32,81 +32,15 @@
 // be inside rho(x | y) <= the k-th distance from y to alive points outside
 // A, which is bounded from per-cell counts and scanned for surviving lower
 // points.
+#include <stdio.h>
+
 #include <type_traits>
 
-#include "search.h"
+#include "rounds.h"
 
 namespace pdd {
 
-struct RoundDev {
-    uint32_t n_alive, n_alive_new, removed, target, m, round, done, err;
-    uint32_t nA, nCand, nDanger, nSurv, nTouch, nResearch, nR, mode;
-    uint32_t sel_need, sel_bin, pad0, pad1;
-    int32_t sel_rem;  // key bits below the first-level prefix
-    uint32_t pool_count, pool_cap, overflow;
-    uint32_t stat_research, stat_danger, stat_touch, stat_surv;
-};
-
-struct RoundArrays {
-    const int4* pts;
-    const uint32_t* cell_of;
-    const uint32_t* coarse_of;
-    uint8_t* alive;
-    uint64_t* cost;
-    int32_t* nbr;       // [n*K]
-    uint8_t* cnt;       // [n]
-    uint32_t* inA;      // round stamps
-    uint32_t* blocked;
-    uint32_t* touched;
-    uint32_t* surv;
-    uint32_t* alive_list[2];
-    uint32_t* A;
-    uint32_t* cand[2];
-    uint32_t* dg_y;      // danger list
-    uint64_t* dg_tc;
-    int32_t* dg_to;
-    uint64_t* dg_dlast;
-    uint32_t* touch_list;
-    uint32_t* research_list;
-    uint32_t* R;
-    uint64_t* ev_cost;
-    int32_t* ev_orig;
-    uint32_t* hist;      // [kSelBins0]
-    uint32_t* rev_off;   // [n+1]
-    int32_t* rev_src;    // [n*K]
-    int32_t* head;       // [n] pool chains
-    int32_t* pool_src;
-    int32_t* pool_next;
-    uint32_t* cell_alive;   // [ncells]
-    uint32_t* cellA;        // [ncells] A points per cell, this round
-    uint32_t* ccell_alive;  // [nccells]
-    uint32_t* ccellA;       // [nccells]
-    uint32_t* ccS;          // [nccells] survivors per coarse cell, this round
-    RoundDev* st;
-    int k, K;
-    float frac;
-    int check;
-};
-
 namespace {
-
-__device__ inline uint32_t wave_append(uint32_t* counter, bool pred) {
-    const uint64_t m = __ballot(pred);
-    const uint32_t lane = lane_id();
-    const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
-    uint32_t base = 0;
-    if (m && lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
-    base = __shfl(base, (int)leader, kWave);
-    return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-}
-
-// First-level bucket of a cost: 0 for 0, else (msb + 1) * 64 + next 6 bits.
-__device__ inline uint32_t bin0(uint64_t c) {
-    if (c == 0) return 0;
-    const int e = 63 - __clzll(c);
-    const uint32_t mant = e >= 6 ? (uint32_t)(c >> (e - 6)) & 63u : (uint32_t)(c << (6 - e)) & 63u;
-    return (uint32_t)(e + 1) * 64u + mant;
-}
 
 // Bits [lo, lo + w) of the 95-bit key (cost << 31 | (2^31 - 1 - orig)).
 __device__ inline uint32_t key_digit(uint64_t c, int32_t orig, int lo, int w) {
@@ -115,32 +49,6 @@ __device__ inline uint32_t key_digit(uint64_t c, int32_t orig, int lo, int w) {
     if (lo >= 31) return (uint32_t)((c >> (lo - 31)) & mask);
     if (lo + w <= 31) return (uint32_t)((inv >> lo) & mask);
     return (uint32_t)(((inv >> lo) | (c << (31 - lo))) & mask);
-}
-
-// Calls f(x, y, z) for every cell of Chebyshev shell r around (cx, cy, cz)
-// inside [0, cm]; returns true when the block of radius r covers [0, cm].
-template <class F>
-__device__ inline bool for_shell(int cx, int cy, int cz, int r, const int32_t* cm, F f) {
-    const int z0 = max(cz - r, 0), z1 = min(cz + r, cm[2]);
-    const int y0 = max(cy - r, 0), y1 = min(cy + r, cm[1]);
-    const int x0 = max(cx - r, 0), x1 = min(cx + r, cm[0]);
-    if (r == 0) {
-        f(cx, cy, cz);
-    } else {
-        for (int z = z0; z <= z1; z++) {
-            const bool zf = (z == cz - r) || (z == cz + r);
-            for (int y = y0; y <= y1; y++) {
-                const bool yf = (y == cy - r) || (y == cy + r);
-                if (zf || yf) {
-                    for (int x = x0; x <= x1; x++) f(x, y, z);
-                } else {
-                    if (cx - r >= 0) f(cx - r, y, z);
-                    if (cx + r <= cm[0]) f(cx + r, y, z);
-                }
-            }
-        }
-    }
-    return cx - r <= 0 && cy - r <= 0 && cz - r <= 0 && cx + r >= cm[0] && cy + r >= cm[1] && cz + r >= cm[2];
 }
 
 // ---------------------------------------------------------------------------
@@ -162,12 +70,14 @@ __global__ void rb_begin(RoundArrays a) {
                 skip = 1;
             } else {
                 const uint32_t B = st->target - st->removed;
-                double want = ceil((double)a.frac * (double)st->n_alive);
+                double want = ceil((double)st->frac * (double)st->n_alive);
                 uint32_t m = want < 1.0 ? 1u : (want > (double)B ? B : (uint32_t)want);
                 st->m = m;
                 st->round++;
                 st->nA = st->nCand = st->nDanger = st->nSurv = st->nTouch = st->nResearch = st->nR = 0;
                 st->mode = 0;
+                st->top_cost = 0;
+                st->top_orig = 0x7FFFFFFF;
             }
         }
     }
@@ -238,10 +148,26 @@ __global__ void __launch_bounds__(kBlock) rb_find0(RoundArrays a) {
         st->sel_bin = b;
         // A = every bin above b when that is not empty; else the exact top m
         // out of bin b (all of the top m lie in it)
-        st->mode = (st->m - need) >= 1 ? 0u : 1u;
+        const uint32_t above = st->m - need;
+        st->mode = above >= 1 ? 0u : 1u;
         st->sel_need = st->m;
         const int e = (int)(b / 64u) - 1;
         st->sel_rem = (e >= 6 ? e - 6 : 0) + 31;
+        // key levels: split the bins above b into kLev parts of about equal count
+        st->lev_t[0] = 0;
+        for (int j = 1; j < kLev; j++) st->lev_t[j] = 0xFFFFFFFFu;
+        for (int j = 0; j < kLev; j++) st->glob_block[j] = 0;
+        if (above >= 1) {
+            uint32_t cum = 0;
+            int j = 1;
+            for (uint32_t bb = b + 1; bb < (uint32_t)kSelBins0 && j < kLev; bb++) {
+                cum += a.hist[bb];
+                while (j < kLev && (uint64_t)cum * kLev >= (uint64_t)above * j) {
+                    st->lev_t[j] = bb + 1;
+                    j++;
+                }
+            }
+        }
     }
 }
 
@@ -364,263 +290,6 @@ __global__ void __launch_bounds__(1024) rb_refine(RoundArrays a) {
 }
 
 // ---------------------------------------------------------------------------
-// blocking
-// ---------------------------------------------------------------------------
-
-// One A point y per lane; its list (ascending distance) staged in LDS with
-// each entry's class: 0 dead, 1 alive outside A, 2 alive in A.
-//  - blocks y when an entry of H(y) is nearer than rho'(y);
-//  - blocks every lower A entry x with fewer than k alive entries not in
-//    H(x) (other than x) within d(x, y) of y;
-//  - puts y on the danger list, with the lowest key a lower point beyond
-//    its list must exceed to be safe, when its list is full and holds fewer
-//    than k entries outside A.
-constexpr int kPairBlock = 64;
-
-template <int K>
-__global__ void __launch_bounds__(kPairBlock) rb_pair(RoundArrays a) {
-    RoundDev* st = a.st;
-    if (st->done || st->err) return;
-    __shared__ uint64_t sd[K][kPairBlock];
-    __shared__ uint64_t sc[K][kPairBlock];
-    __shared__ int32_t so[K][kPairBlock];
-    __shared__ uint32_t sz[K][kPairBlock];
-    __shared__ uint8_t scls[K][kPairBlock];
-    const uint32_t nA = st->nA, round = st->round;
-    const int k = a.k;
-    const int l = threadIdx.x;
-    const uint32_t n_it = (nA + kPairBlock - 1) / kPairBlock * kPairBlock;
-    for (uint32_t t = blockIdx.x * kPairBlock + l; t < n_it; t += gridDim.x * kPairBlock) {
-        bool danger = false;
-        uint32_t y = 0;
-        uint64_t tc = 0, dlast = 0;
-        int32_t to = 0;
-        if (t < nA) {
-            y = a.A[t];
-            const int4 py = a.pts[y];
-            const uint64_t cy = a.cost[y];
-            const int32_t oy = py.w;
-            const int c = a.cnt[y];
-            const int32_t* nb = a.nbr + (size_t)y * K;
-            int nL = 0, nAe = 0;
-            for (int j = 0; j < K; j++) {
-                uint8_t cls = 0;
-                uint64_t d = ~0ull;
-                uint32_t z = 0;
-                if (j < c) {
-                    z = (uint32_t)nb[j];
-                    const int4 pz = a.pts[z];
-                    const uint64_t dz = dist2(py.x, py.y, py.z, pz.x, pz.y, pz.z);
-                    dlast = dz;
-                    if (a.alive[z]) {
-                        d = dz;
-                        if (a.inA[z] == round) {
-                            cls = 2;
-                            nAe++;
-                            sc[j][l] = a.cost[z];
-                            so[j][l] = pz.w;
-                        } else {
-                            cls = 1;
-                            nL++;
-                        }
-                    }
-                }
-                sd[j][l] = d;
-                scls[j][l] = cls;
-                sz[j][l] = z;
-            }
-            const bool complete = c < K;
-            // y itself
-            int low = 0;
-            uint64_t dH = ~0ull, rho = ~0ull;
-            for (int j = 0; j < K; j++) {
-                const uint8_t cls = scls[j][l];
-                if (cls == 0) continue;
-                if (cls == 2 && key_above(sc[j][l], so[j][l], cy, oy)) {
-                    if (dH == ~0ull) dH = sd[j][l];
-                } else if (++low == k) {
-                    rho = sd[j][l];
-                    break;
-                }
-            }
-            bool blocked_self;
-            if (low >= k) blocked_self = dH < rho;
-            else if (complete) blocked_self = dH != ~0ull;
-            else blocked_self = true;  // implies higher entries at or before the list's end
-            if (blocked_self) a.blocked[y] = round;
-            // lower A entries of the list
-            for (int j = 0; j < K; j++) {
-                if (scls[j][l] != 2) continue;
-                const uint64_t cj = sc[j][l];
-                const int32_t oj = so[j][l];
-                if (key_above(cj, oj, cy, oy)) continue;
-                const uint64_t dj = sd[j][l];
-                int q = 0;
-                for (int i = 0; i < K; i++) {
-                    if (i == j) continue;
-                    const uint8_t ci = scls[i][l];
-                    if (ci == 0) continue;
-                    if (sd[i][l] > dj) break;
-                    if (ci == 1 || key_above(cj, oj, sc[i][l], so[i][l])) q++;
-                }
-                const bool covered = complete || dj < dlast;
-                if (q < k || !covered) a.blocked[sz[j][l]] = round;
-            }
-            // lower points beyond the list
-            if (!complete && nL < k) {
-                danger = true;
-                const int need = k - nL;
-                if (nAe < need) {
-                    tc = cy;
-                    to = oy;
-                } else {
-                    // need-th lowest key among the alive A entries
-                    bool have = false;
-                    uint64_t pc = 0;
-                    int32_t po = 0;
-                    for (int r = 0; r < need; r++) {
-                        bool found = false;
-                        uint64_t bc = 0;
-                        int32_t bo = 0;
-                        for (int j = 0; j < K; j++) {
-                            if (scls[j][l] != 2) continue;
-                            const uint64_t cz = sc[j][l];
-                            const int32_t oz = so[j][l];
-                            if (have && !key_above(cz, oz, pc, po)) continue;
-                            if (!found || key_above(bc, bo, cz, oz)) {
-                                bc = cz;
-                                bo = oz;
-                                found = true;
-                            }
-                        }
-                        pc = bc;
-                        po = bo;
-                        have = true;
-                    }
-                    tc = pc;
-                    to = po;
-                }
-            }
-        }
-        const uint32_t p = wave_append(&st->nDanger, danger);
-        if (danger) {
-            a.dg_y[p] = y;
-            a.dg_tc[p] = tc;
-            a.dg_to[p] = to;
-            a.dg_dlast[p] = dlast;
-        }
-    }
-}
-
-__global__ void __launch_bounds__(kBlock) rb_survive(RoundArrays a) {
-    RoundDev* st = a.st;
-    if (st->done || st->err) return;
-    const uint32_t nA = st->nA, round = st->round;
-    const uint32_t n_it = (nA + blockDim.x - 1) / blockDim.x * blockDim.x;
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_it; t += gridDim.x * blockDim.x) {
-        bool sv = false;
-        if (t < nA) {
-            const uint32_t x = a.A[t];
-            atomicAdd(&a.cellA[a.cell_of[x]], 1u);
-            atomicAdd(&a.ccellA[a.coarse_of[x]], 1u);
-            if (a.blocked[x] != round) {
-                sv = true;
-                a.surv[x] = round;
-                atomicAdd(&a.ccS[a.coarse_of[x]], 1u);
-            }
-        }
-        wave_append(&st->nSurv, sv);
-    }
-}
-
-// A dangerous y blocks every surviving lower x with key <= its threshold,
-// at or beyond its list's last distance and nearer than R, where R bounds
-// the k-th distance from y to alive points outside A: the smallest cell
-// block around y holding k such points (per-cell counts) gives it.
-__global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
-    RoundDev* st = a.st;
-    if (st->done || st->err || st->nSurv == 0) return;
-    const uint32_t nd = st->nDanger, round = st->round;
-    const int k = a.k;
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nd; t += gridDim.x * blockDim.x) {
-        const uint32_t y = a.dg_y[t];
-        const uint64_t tc = a.dg_tc[t], dlast = a.dg_dlast[t];
-        const int32_t to = a.dg_to[t];
-        const int4 py = a.pts[y];
-        const uint64_t cy = a.cost[y];
-        const int32_t oy = py.w;
-        const int ux = py.x - g.minx, uy = py.y - g.miny, uz = py.z - g.minz;
-        uint64_t R2 = 0;
-        bool inf = false, found = false;
-        {
-            uint32_t cntL = 0;
-            const LevelView& l0 = g.lv[0];
-            const int fx = ux >> l0.s, fy = uy >> l0.s, fz = uz >> l0.s;
-            for (int r = 0; r <= 2 && !found && !inf; r++) {
-                const bool cover = for_shell(fx, fy, fz, r, l0.cmax, [&](int x, int yy, int z) {
-                    const uint32_t c =
-                        hash_find(l0.hkeys, l0.hvals, l0.hmask, morton3((uint32_t)x, (uint32_t)yy, (uint32_t)z));
-                    if (c != kNone) cntL += a.cell_alive[c] - a.cellA[c];
-                });
-                if (cntL >= (uint32_t)k) {
-                    const uint64_t e = (uint64_t)(r + 1) << l0.s;
-                    R2 = 3 * e * e;
-                    found = true;
-                } else if (cover) {
-                    inf = true;
-                }
-            }
-            cntL = 0;
-            const LevelView& l1 = g.lv[1];
-            const int qx = ux >> l1.s, qy = uy >> l1.s, qz = uz >> l1.s;
-            for (int r = 0; !found && !inf; r++) {
-                const bool cover = for_shell(qx, qy, qz, r, l1.cmax, [&](int x, int yy, int z) {
-                    const uint32_t c =
-                        hash_find(l1.hkeys, l1.hvals, l1.hmask, morton3((uint32_t)x, (uint32_t)yy, (uint32_t)z));
-                    if (c != kNone) cntL += a.ccell_alive[c] - a.ccellA[c];
-                });
-                if (cntL >= (uint32_t)k) {
-                    const uint64_t e = (uint64_t)(r + 1) << l1.s;
-                    R2 = 3 * e * e;
-                    found = true;
-                } else if (cover || r >= 4) {
-                    inf = true;  // far or unbounded: every surviving lower point is checked
-                }
-            }
-        }
-        auto consider = [&](uint32_t x) {
-            if (x == y || a.surv[x] != round) return;
-            const int4 px = a.pts[x];
-            const uint64_t d = dist2(px.x, px.y, px.z, py.x, py.y, py.z);
-            if (d < dlast || (!inf && d >= R2)) return;
-            const uint64_t cx = a.cost[x];
-            if (key_above(cx, px.w, cy, oy) || key_above(cx, px.w, tc, to)) return;
-            a.blocked[x] = round;
-        };
-        if (inf) {
-            const uint32_t nA = st->nA;
-            for (uint32_t u = 0; u < nA; u++) consider(a.A[u]);
-            continue;
-        }
-        const int ri = (int)sqrt((double)R2) + 1;
-        const LevelView& l1 = g.lv[1];
-        const int sc = l1.s;
-        const int x0 = max((ux - ri) >> sc, 0), x1 = min((ux + ri) >> sc, l1.cmax[0]);
-        const int y0 = max((uy - ri) >> sc, 0), y1 = min((uy + ri) >> sc, l1.cmax[1]);
-        const int z0 = max((uz - ri) >> sc, 0), z1 = min((uz + ri) >> sc, l1.cmax[2]);
-        for (int zz = z0; zz <= z1; zz++)
-            for (int yy = y0; yy <= y1; yy++)
-                for (int xx = x0; xx <= x1; xx++) {
-                    const uint32_t c =
-                        hash_find(l1.hkeys, l1.hvals, l1.hmask, morton3((uint32_t)xx, (uint32_t)yy, (uint32_t)zz));
-                    if (c == kNone || a.ccS[c] == 0) continue;
-                    for (uint32_t j = l1.start[c]; j < l1.start[c + 1]; j++) consider(j);
-                }
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&st->stat_danger, nd);
-}
-
-// ---------------------------------------------------------------------------
 // removal and re-costing
 // ---------------------------------------------------------------------------
 
@@ -635,9 +304,19 @@ __global__ void __launch_bounds__(kBlock) rb_remove(RoundArrays a) {
         if (t < nA) {
             x = a.A[t];
             rm = a.blocked[x] != round;
-            a.cellA[a.cell_of[x]] = 0;
-            a.ccellA[a.coarse_of[x]] = 0;
-            a.ccS[a.coarse_of[x]] = 0;
+            if (rm) {
+                // a dangerous point with no bound for this level makes every
+                // survivor of the level at or below its cost wait (except the
+                // round's highest key, which no point can precede)
+                const uint64_t cx = a.cost[x];
+                const bool top = cx == st->top_cost && a.pts[x].w == st->top_orig;
+                rm = top || cx >= st->glob_block[level_of(st, cx)];
+            }
+#pragma unroll
+            for (int j = 0; j < kLev; j++) {
+                a.cellAlev[(size_t)a.cell_of[x] * kLev + j] = 0;
+                a.ccellAlev[(size_t)a.coarse_of[x] * kLev + j] = 0;
+            }
         }
         const uint32_t p = wave_append(&st->nR, rm);
         if (rm) {
@@ -657,6 +336,11 @@ __global__ void rb_remove_end(RoundArrays a) {
     if (st->nR == 0) st->err = 5;  // the top key is never blocked
     st->removed += st->nR;
     st->stat_surv += st->nSurv;
+    // adapt the ranked share: a round that frees few of A (a dense region
+    // filling A) ranks fewer points next time; a productive one more
+    const float yield = (float)st->nR / (float)(st->nA ? st->nA : 1);
+    if (yield < 0.05f) st->frac = fmaxf(st->frac * 0.5f, 1e-5f);
+    else if (yield > 0.2f) st->frac = fminf(st->frac * 1.5f, st->frac_max);
 }
 
 __device__ inline void touch(const RoundArrays& a, RoundDev* st, uint32_t z, uint32_t round) {
@@ -715,33 +399,41 @@ __global__ void __launch_bounds__(kBlock) rb_recost(RoundArrays a) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&st->stat_touch, nt);
 }
 
+// New list of z over the alive points: one wavefront per point.
 template <int K>
 __global__ void __launch_bounds__(kBlock) rb_research(RoundArrays a, GridView g) {
     RoundDev* st = a.st;
     if (st->done || st->err) return;
+    __shared__ uint32_t lds[kBlock / kWave][2][kWave];
     const uint32_t nr = st->nResearch;
     const int k = a.k;
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nr; t += gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const uint32_t nw = gridDim.x * (kBlock / kWave);
+    for (uint32_t t = blockIdx.x * (kBlock / kWave) + w; t < nr; t += nw) {
         const uint32_t z = a.research_list[t];
         const int4 pz = a.pts[z];
-        TopK<K> tk;
-        tk.init();
         SearchCtx sc{a.alive, nullptr, 0};
-        ring_search<K, kAlive>(g, z, pz, sc, tk, K);
-        const int c = tk.count();
-        int32_t* nb = a.nbr + (size_t)z * K;
-#pragma unroll
-        for (int j = 0; j < K; j++) nb[j] = tk.id[j];
-        a.cnt[z] = (uint8_t)c;
-        const uint64_t w = list_cost<K>(tk, c < k ? c : k);
-        if (a.check && w > a.cost[z]) st->err = 7;
-        a.cost[z] = w;
+        uint64_t d;
+        int32_t id;
+        wave_knn<K, kAlive>(g, z, pz, sc, K, d, id, lds[w][0], lds[w][1]);
+        const int c = __popcll(__ballot(lane < K && d != ~0ull));
+        const int use = c < k ? c : k;
+        const uint64_t wsum = wave_sum64(lane < use ? cost_term(d) : 0ull);
+        if (lane < K) a.nbr[(size_t)z * K + lane] = id;
+        if (lane == 0) {
+            a.cnt[z] = (uint8_t)c;
+            if (a.check && wsum > a.cost[z]) st->err = 7;
+            a.cost[z] = wsum;
+        }
         // reverse edges of the new members
-        for (int j = 0; j < c; j++) {
-            const uint32_t node = atomicAdd(&st->pool_count, 1u);
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&st->pool_count, (uint32_t)c);
+        base = (uint32_t)__shfl((int)base, 0, kWave);
+        if (lane < c) {
+            const uint32_t node = base + (uint32_t)lane;
             if (node < st->pool_cap) {
                 a.pool_src[node] = (int32_t)z;
-                a.pool_next[node] = atomicExch(&a.head[nb[j]], (int32_t)node);
+                a.pool_next[node] = atomicExch(&a.head[id], (int32_t)node);
             } else {
                 st->overflow = 1;
             }
@@ -801,11 +493,13 @@ __global__ void rev_reset_k(RoundArrays a) {
 // setup and finalisation
 // ---------------------------------------------------------------------------
 
-__global__ void rd_init(RoundDev* st, uint32_t n, uint32_t target, uint32_t pool_cap) {
+__global__ void rd_init(RoundDev* st, uint32_t n, uint32_t target, uint32_t pool_cap, float frac) {
     RoundDev z = {};
     z.n_alive = n;
     z.target = target;
     z.pool_cap = pool_cap;
+    z.frac = frac;
+    z.frac_max = frac;
     *st = z;
 }
 
@@ -867,7 +561,8 @@ enum {
     kSAlive = 10, kSCost, kSNbr, kSCnt, kSInA, kSBlocked, kSTouched, kSAl0, kSAl1, kSA, kSC0, kSC1, kSDgY,
     kSTouch, kSResearch, kSR, kSEvC, kSEvO, kSHist, kSRevOff, kSRevSrc, kSHead, kSPoolS, kSPoolN, kSSt, kSTmp,
     kSFin1, kSFin2, kSSurv,
-    kSCellAlive = 60, kSCellA, kSCCellAlive, kSCCellA, kSCCS, kSDgC, kSDgO, kSDgD
+    kSCellAlive = 60, kSCellA, kSCCellAlive, kSCCellA, kSCCS, kSDgC, kSDgO, kSDgD, kSSurvOff, kSSurvList,
+    kSSurvBucket
 };
 static_assert(kSSurv < 40, "scratch slots overlap the scan's");
 
@@ -896,9 +591,9 @@ int launch_round(Ctx* c, RoundArrays& a, const GridView& g, int par) {
     hipLaunchKernelGGL(rb_find0, dim3(1), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_collect0, dim3(G), dim3(kBlock), 0, c->stream, a, par);
     hipLaunchKernelGGL(rb_refine, dim3(1), dim3(1024), 0, c->stream, a);
-    hipLaunchKernelGGL(rb_pair<K>, dim3(2048), dim3(kPairBlock), 0, c->stream, a);
-    hipLaunchKernelGGL(rb_survive, dim3(G), dim3(kBlock), 0, c->stream, a);
-    hipLaunchKernelGGL(rb_danger, dim3(G), dim3(kBlock), 0, c->stream, a, g);
+    PDD_HIP(c, hipGetLastError());
+    int rc = launch_blocking(c, a, g, K);
+    if (rc) return rc;
     hipLaunchKernelGGL(rb_remove, dim3(G), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_remove_end, dim3(1), dim3(1), 0, c->stream, a);
     hipLaunchKernelGGL(rb_touch, dim3(G), dim3(kBlock), 0, c->stream, a);
@@ -930,7 +625,15 @@ int run_rounds(Ctx* c, RoundArrays& a, const GridView& g, uint32_t n) {
             c->stats[7] = hst->stat_touch;
             return PDD_OK;
         }
-        if (hst->overflow) {
+        if (c->progress && (hst->round % 50 == 0)) {
+            fprintf(stderr, "pdd: round %u removed %u/%u alive %u A %u removed-now %u danger %u survivors %u "
+                    "researched %u\n", hst->round, hst->removed, hst->target, hst->n_alive_new, hst->nA, hst->nR,
+                    hst->nDanger, hst->nSurv, hst->nResearch);
+            fflush(stderr);
+        }
+        // rebuild the reverse lists when the appended chains overflowed or
+        // grew longer than one node per alive point on average
+        if (hst->overflow || hst->pool_count > hst->n_alive_new) {
             if ((rc = build_reverse(c, a, n))) return rc;
             c->stats[3]++;
         }
@@ -992,10 +695,14 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, int6
     ALLOC(pool_src, kSPoolS, pool_cap * 4);
     ALLOC(pool_next, kSPoolN, pool_cap * 4);
     ALLOC(cell_alive, kSCellAlive, (size_t)ncells * 4);
-    ALLOC(cellA, kSCellA, (size_t)ncells * 4);
+    ALLOC(cellAlev, kSCellA, (size_t)ncells * kLev * 4);
     ALLOC(ccell_alive, kSCCellAlive, (size_t)nccells * 4);
-    ALLOC(ccellA, kSCCellA, (size_t)nccells * 4);
-    ALLOC(ccS, kSCCS, (size_t)nccells * 4);
+    ALLOC(ccellAlev, kSCCellA, (size_t)nccells * kLev * 4);
+    ALLOC(ccS, kSCCS, (size_t)(nccells + 1) * 4);
+    ALLOC(surv_off, kSSurvOff, (size_t)(nccells + 1) * 4);
+    ALLOC(surv_list, kSSurvList, (size_t)n * 4);
+    ALLOC(surv_bucket, kSSurvBucket, (size_t)n * 4);
+    a.nccells = nccells;
     ALLOC(st, kSSt, sizeof(RoundDev));
 #undef ALLOC
     int rc;
@@ -1004,15 +711,15 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, int6
     if ((rc = fill_u32(c, a.blocked, 0, n))) return rc;
     if ((rc = fill_u32(c, a.touched, 0, n))) return rc;
     if ((rc = fill_u32(c, a.surv, 0, n))) return rc;
-    if ((rc = fill_u32(c, a.cellA, 0, ncells))) return rc;
-    if ((rc = fill_u32(c, a.ccellA, 0, nccells))) return rc;
-    if ((rc = fill_u32(c, a.ccS, 0, nccells))) return rc;
+    if ((rc = fill_u32(c, a.cellAlev, 0, (size_t)ncells * kLev))) return rc;
+    if ((rc = fill_u32(c, a.ccellAlev, 0, (size_t)nccells * kLev))) return rc;
+    if ((rc = fill_u32(c, a.ccS, 0, nccells + 1))) return rc;
     if ((rc = iota_u32(c, a.alive_list[0], n))) return rc;
     hipLaunchKernelGGL(cell_count_k, dim3(gfor(ncells)), dim3(kBlock), 0, c->stream, g.lv[0].start, ncells,
                        a.cell_alive);
     hipLaunchKernelGGL(cell_count_k, dim3(gfor(nccells)), dim3(kBlock), 0, c->stream, g.lv[1].start, nccells,
                        a.ccell_alive);
-    hipLaunchKernelGGL(rd_init, dim3(1), dim3(1), 0, c->stream, a.st, n, target, (uint32_t)pool_cap);
+    hipLaunchKernelGGL(rd_init, dim3(1), dim3(1), 0, c->stream, a.st, n, target, (uint32_t)pool_cap, frac);
     PDD_HIP(c, hipGetLastError());
 
     KnnOut ko{a.nbr, a.cnt, a.cost, nullptr};

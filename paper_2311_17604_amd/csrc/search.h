@@ -148,6 +148,153 @@ __device__ int ring_search(const GridView& g, uint32_t q, int4 qp, const SearchC
     return g.nlev;  // not reached: the top level's block grows until it covers the grid
 }
 
+// ---------------------------------------------------------------------------
+// One wavefront per query.  The 64 lanes look up the cells of a shell at
+// once, pack the points of the found cells into chunks of 64 (a wave prefix
+// sum over the cell sizes, then a binary search per lane), and test one
+// point each.  The top-K list is spread over the lanes (lane j holds the
+// j-th nearest); a candidate below the K-th distance is inserted with one
+// ballot (its rank) and one lane shift.  Same levels, shells and
+// certification as ring_search, same tie rule as TopK.
+// ---------------------------------------------------------------------------
+
+__device__ inline uint64_t readlane64(uint64_t v, int l) {
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t shfl_up64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, 1, kWave);
+    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), 1, kWave);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// lds_start / lds_excl: 64 entries of wave-private LDS each.  On return lane
+// j < K holds the j-th nearest (my_d = ~0 past the end).
+template <int K, int MODE>
+__device__ void wave_knn(const GridView& g, uint32_t q, int4 qp, const SearchCtx& sc, int kcert, uint64_t& my_d,
+                         int32_t& my_id, uint32_t* lds_start, uint32_t* lds_excl) {
+    const int lane = (int)lane_id();
+    const int ux = qp.x - g.minx, uy = qp.y - g.miny, uz = qp.z - g.minz;
+    my_d = ~0ull;
+    my_id = -1;
+    for (int L = 0; L < g.nlev; L++) {
+        const LevelView& lv = g.lv[L];
+        const int s = lv.s;
+        const int cx = ux >> s, cy = uy >> s, cz = uz >> s;
+        const int rmax = (L == g.nlev - 1) ? (1 << 22) : 2;
+        if (L > 0) {
+            my_d = ~0ull;
+            my_id = -1;
+        }
+        for (int r = 0; r <= rmax; r++) {
+            const int side = 2 * r + 1;
+            const int ncube = side * side * side;
+            for (int base = 0; base < ncube; base += kWave) {
+                const int idx = base + lane;
+                uint32_t st = 0, cnt = 0;
+                if (idx < ncube) {
+                    const int dz = idx / (side * side) - r;
+                    const int rem = idx % (side * side);
+                    const int dy = rem / side - r, dx = rem % side - r;
+                    const int m = max(abs(dx), max(abs(dy), abs(dz)));
+                    const int x = cx + dx, y = cy + dy, z = cz + dz;
+                    if (m == r && x >= 0 && y >= 0 && z >= 0 && x <= lv.cmax[0] && y <= lv.cmax[1] &&
+                        z <= lv.cmax[2]) {
+                        const uint32_t c =
+                            hash_find(lv.hkeys, lv.hvals, lv.hmask, morton3((uint32_t)x, (uint32_t)y, (uint32_t)z));
+                        if (c != kNone) {
+                            st = lv.start[c];
+                            cnt = lv.start[c + 1] - st;
+                        }
+                    }
+                }
+                uint32_t incl = cnt;
+#pragma unroll
+                for (int o = 1; o < kWave; o <<= 1) {
+                    const uint32_t v = (uint32_t)__shfl_up((int)incl, o, kWave);
+                    if (lane >= o) incl += v;
+                }
+                const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+                if (total == 0) continue;
+                lds_start[lane] = st;
+                lds_excl[lane] = incl - cnt;
+                wave_sync_lds();
+                for (uint32_t t0 = 0; t0 < total; t0 += kWave) {
+                    const uint32_t t = t0 + (uint32_t)lane;
+                    uint64_t d = ~0ull;
+                    uint32_t j = 0;
+                    if (t < total) {
+                        int l = 0;
+#pragma unroll
+                        for (int step = 32; step > 0; step >>= 1)
+                            if (lds_excl[l + step] <= t) l += step;
+                        j = lds_start[l] + (t - lds_excl[l]);
+                        bool ok = j != q;
+                        if (MODE != kAll && ok) {
+                            ok = sc.alive[j] != 0;
+                            if (MODE == kAliveNotA && ok) ok = sc.inA[j] != sc.round;
+                        }
+                        if (ok) {
+                            const int4 p = g.pts[j];
+                            d = dist2(qp.x, qp.y, qp.z, p.x, p.y, p.z);
+                        }
+                    }
+                    uint64_t thr = readlane64(my_d, K - 1);
+                    uint64_t m = __ballot(d < thr);
+                    while (m) {
+                        const int l2 = __ffsll((unsigned long long)m) - 1;
+                        m &= m - 1;
+                        const uint64_t dv = readlane64(d, l2);
+                        const int32_t iv = __builtin_amdgcn_readlane((int)j, l2);
+                        const int p = __popcll(__ballot(lane < K && my_d <= dv));
+                        if (p < K) {
+                            const uint64_t upd = shfl_up64(my_d);
+                            const int32_t upi = __shfl_up(my_id, 1, kWave);
+                            if (lane == p) {
+                                my_d = dv;
+                                my_id = iv;
+                            } else if (lane > p && lane < K) {
+                                my_d = upd;
+                                my_id = upi;
+                            }
+                            thr = readlane64(my_d, K - 1);
+                            m &= __ballot(d < thr);
+                        }
+                    }
+                }
+                wave_sync_lds();
+            }
+            uint64_t g2 = face_gap2(ux, cx, r, s, lv.cmax[0]);
+            const uint64_t gy = face_gap2(uy, cy, r, s, lv.cmax[1]);
+            const uint64_t gz = face_gap2(uz, cz, r, s, lv.cmax[2]);
+            if (gy < g2) g2 = gy;
+            if (gz < g2) g2 = gz;
+            if (g2 == ~0ull) return;
+            const uint64_t kth = readlane64(my_d, kcert - 1);
+            if (kth != ~0ull && kth <= g2) return;
+        }
+    }
+}
+
+// Sum over lanes of v (wave-uniform result).
+__device__ inline uint64_t wave_sum64(uint64_t v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o, kWave);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o, kWave);
+        v += ((uint64_t)hi << 32) | lo;
+    }
+    return v;
+}
+
 // Cost of a sorted neighbour list: sum of cost_term over its first `use` entries.
 template <int K>
 __device__ inline uint64_t list_cost(const TopK<K>& t, int use) {

@@ -1,13 +1,16 @@
 """The exact parallel round rule, as a small numpy model, against the oracle.
 
-A round takes the m <= B highest keys A (B = removals still to do), the rest
-L, and for x in A the radius rho2(x) = k-th smallest d2 from x to L - {x}.
-x in A is blocked if some y in A with a higher key has d2(x, y) < rho2(x)
-or d2(x, y) < rho2(y); every unblocked x is removed at once with its current
-cost.  Costs never rise after a removal (Sec. 5, step 2), which makes the
-result equal to the sequential greedy's (Sec. 4) for any m.  The GPU rounds
-implement this rule; these cases also keep the two counterexamples to a
-rule without rho2 and without m <= B.
+A round takes the m <= B highest keys A (B = removals still to do).  For x
+in A let H(x) be the points of A above x, rho'(x) the k-th smallest d2 from
+x to the alive points not in H(x) (x excluded), and rho(x | y) the k-th
+smallest d2 from y to the alive points not in H(x) (x, y excluded).  x is
+blocked if some y in H(x) has d2(x, y) < rho'(x) or d2(x, y) < rho(x | y);
+every unblocked x is removed at once with its current cost.  Costs never
+rise after a removal (Sec. 5, step 2), which makes the result equal to the
+sequential greedy's (Sec. 4) for any m.  The GPU rounds implement this rule
+(blocking more where their stored lists cannot decide).  The cases also keep
+the weaker rule that measures both radii to L = alive minus A, and the two
+counterexamples to a rule without such radii and without m <= B.
 """
 import numpy as np
 import pytest
@@ -31,7 +34,12 @@ def _costs(D, alive, k):
     return W
 
 
-def round_model(P, k, keep, frac):
+def _kth(D, i, pool, k):
+    pool = [z for z in pool if z != i]
+    return np.sort(D[i, pool])[k - 1] if len(pool) >= k else np.inf
+
+
+def round_model(P, k, keep, frac, rule="stable"):
     n = len(P)
     D = _d2(P)
     alive = np.ones(n, bool)
@@ -43,17 +51,24 @@ def round_model(P, k, keep, frac):
         W = _costs(D, alive, k)
         S = sorted(W, key=lambda i: (-W[i], i))
         m = min(B, max(1, int(np.ceil(frac * len(S)))))
-        A, L = S[:m], np.array(S[m:], dtype=np.int64)
+        A, L = S[:m], S[m:]
         rank = {x: r for r, x in enumerate(S)}  # lower rank = higher key
-        rho2 = {}
-        for x in A:
-            others = L[L != x]
-            rho2[x] = np.sort(D[x, others])[k - 1] if len(others) >= k else np.inf
         blocked = set()
         for x in A:
-            for y in A:
-                if y != x and rank[y] < rank[x] and (D[x, y] < rho2[x] or D[x, y] < rho2[y]):
-                    blocked.add(x)
+            H = S[:rank[x]]
+            if rule == "stable":
+                rest = S[rank[x]:]          # not above x (x itself dropped by _kth)
+                rx = _kth(D, x, rest, k)
+                for y in H:
+                    if D[x, y] < rx or D[x, y] < _kth(D, y, [z for z in rest if z != x], k):
+                        blocked.add(x)
+                        break
+            else:
+                rx = _kth(D, x, L, k)
+                for y in H:
+                    if D[x, y] < rx or D[x, y] < _kth(D, y, L, k):
+                        blocked.add(x)
+                        break
         R = [x for x in A if x not in blocked]
         assert R, "the top key is never blocked"
         for x in R:
@@ -107,10 +122,11 @@ def _cases():
 
 
 @pytest.mark.parametrize("k,n,box,keep,frac,seed", _cases())
-def test_round_rule_equals_sequential_greedy(oracle_mod, k, n, box, keep, frac, seed):
+@pytest.mark.parametrize("rule", ["stable", "outside_A"])
+def test_round_rule_equals_sequential_greedy(oracle_mod, k, n, box, keep, frac, seed, rule):
     P = scangen.random_cloud(n, box, seed)
     kept, order, oc = oracle_mod.decimate(P, k, keep, b=2)
-    mk, mo, mc, _ = round_model(P, k, keep, frac)
+    mk, mo, mc, _ = round_model(P, k, keep, frac, rule)
     assert np.array_equal(kept, mk)
     assert list(order) == mo
     assert [int(c) for c in oc] == mc
@@ -122,6 +138,18 @@ def test_round_rule_on_scan_crop_takes_few_rounds(oracle_mod):
     mk, mo, mc, rounds = round_model(P, 8, 75, 0.05)
     assert np.array_equal(kept, mk) and list(order) == mo
     assert rounds < 225 / 2
+
+
+def test_stable_rule_needs_fewer_rounds_on_polar_cluster(oracle_mod):
+    """Near-duplicate cluster of the top scan row: counting lower points of A
+    as stable neighbours frees most of the cluster at once."""
+    P = scangen.config(1, scale=0.25).xyz
+    Q = P[np.sort(np.argsort(-P[:, 2].astype(np.int64))[:160])]
+    kept, order, _ = oracle_mod.decimate(Q, 4, 40, b=2)
+    a = round_model(Q, 4, 40, 0.3, "stable")
+    b = round_model(Q, 4, 40, 0.3, "outside_A")
+    assert np.array_equal(a[0], kept) and np.array_equal(b[0], kept) and a[1] == list(order)
+    assert a[3] < b[3]
 
 
 def test_counterexample_budget(oracle_mod):
