@@ -2,11 +2,20 @@
 
 A step is one pdd_decimate call on device-resident synthetic input: voxel
 grid, initial k-NN costs, removal rounds and finalisation, producing the kept
-indices and the removal order.  Prints one JSON line.
+indices and the removal order.  Prints one JSON line with
+
+  roofline      the k-NN cost kernel: algorithmic bytes per launch (read one
+                16-byte point, write its K-entry list, cost and count) over
+                its average duration from HIP events recorded on the
+                library's stream; traffic from the rocprofv3 counter summary
+                in profiles/ when it matches the kernel source;
+  cpu_baseline  the CPU oracle (one core) on a bounded window of the same
+                scan.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -15,11 +24,57 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "knn_cost_counters.json")
+KNN_SOURCES = ("paper_2311_17604_amd/csrc/knn.hip", "paper_2311_17604_amd/csrc/search.h")
+
+
+def knn_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KNN_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per k-NN launch from the committed counter summary, or None
+    when it is missing, for another workload, or for another kernel source."""
+    if not os.path.exists(COUNTERS):
+        return None
+    c = json.load(open(COUNTERS))
+    if c.get("workload") != workload or c.get("source_sha") != knn_source_hash():
+        return None
+    return c.get("traffic_bytes")
+
+
+def cpu_baseline(w, rows_cols):
+    """Oracle points/s on an angular window of the scan (rows x columns of the
+    ray grid), one core."""
+    import numpy as np
+
+    from oracle import oracle
+    if not os.path.exists(oracle.LIB):
+        oracle.build()
+    R, C = rows_cols
+    r0, r1, c0, c1 = R * 2 // 5, R * 2 // 5 + R // 7, 0, C // 6
+    idx = (np.arange(r0, r1)[:, None] * C + np.arange(c0, c1)[None, :]).ravel()
+    P = np.ascontiguousarray(w.xyz[idx])
+    keep = max(1, len(P) * w.keep // len(w.xyz))
+    t = time.perf_counter()
+    oracle.decimate(P, w.k, keep, b=8)
+    dt = time.perf_counter() - t
+    return {"value": len(P) / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": "rows %d-%d x columns %d-%d of the %dx%d ray grid (%d points, keep %d, k=%d), %.1f s"
+                      % (r0, r1, c0, c1, R, C, len(P), keep, w.k, dt)}
+
+
+GRIDS = {1: (500, 400), 2: (5000, 4000)}
+
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2, help="workload 1..5 (2: 20M-point scan, k=16, keep 10%%)")
     ap.add_argument("--scale", type=float, default=1.0)
@@ -28,13 +83,23 @@ def main():
     ap.add_argument("--b", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true", help="no per-50-round progress lines from the library")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run four 1 GiB device-to-device copies (scales the HBM byte counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "copies": 4}))
+        return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding).",
-              file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU path (DESIGN.md explains how it would "
+              "shard).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2311_17604_amd import pdd, scangen
@@ -48,8 +113,8 @@ def main():
     kept = torch.empty(w.keep, dtype=torch.int32, device="cuda")
     order = torch.empty(n - w.keep, dtype=torch.int32, device="cuda")
     oc = torch.empty(n - w.keep, dtype=torch.int64, device="cuda")
-    kw = dict(b=args.b, voxel_log2=args.voxel_log2, round_frac=args.round_frac, out=(kept, order, oc), timing=True,
-              progress=not args.quiet)
+    kw = dict(b=args.b, voxel_log2=args.voxel_log2, round_frac=args.round_frac, out=(kept, order, oc),
+              timing=True, progress=not args.quiet)
     for i in range(args.warmup):
         pdd.decimate(ctx, x, w.keep, w.k, **kw)
         print("warmup %d done" % i, file=sys.stderr, flush=True)
@@ -63,6 +128,25 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = ctx.stats()
+    ph = {p: round(sum(q[p] for q in phases) / len(phases), 3) for p in phases[0]}
+
+    # k-NN cost kernel: one launch per step
+    K = st["list_width"]
+    bytes_per_point = 16 + 4 * K + 8 + 1
+    algo = n * bytes_per_point
+    knn_ms = ph["knn"]
+    achieved = algo / (knn_ms * 1e-3) / 1e9
+    workload = w.name if args.scale == 1.0 else "%s@%g" % (w.name, args.scale)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(workload),
+            "kernel": "knn_wave_k<%d>" % K, "algorithmic_bytes_per_launch": algo,
+            "bytes_per_point": bytes_per_point, "avg_launch_ms": knn_ms}
+
+    cpu = None
+    if not args.no_cpu_baseline and args.config in GRIDS and args.scale == 1.0:
+        print("cpu baseline: oracle on a window of the scan", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w, GRIDS[args.config])
+
     rec = {
         "metric": "input points decimated/s at 1 MI355X (learned+batched vs plain), bit-exact",
         "value": n * args.steps / dt,
@@ -76,9 +160,10 @@ def main():
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": w.name, "n": n, "k": w.k, "keep": w.keep, "method": "plain",
-                   "gen_s": round(t_gen, 2), "stats": st,
-                   "phase_ms": {p: round(sum(ph[p] for ph in phases) / len(phases), 3) for p in phases[0]}},
+        "config": {"workload": workload, "n": n, "k": w.k, "keep": w.keep, "method": "plain",
+                   "gen_s": round(t_gen, 2), "stats": st, "phase_ms": ph},
+        "roofline": roof,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
     ctx.close()

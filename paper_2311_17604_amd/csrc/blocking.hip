@@ -109,10 +109,11 @@ __global__ void __launch_bounds__(kBlock) rb_survive(RoundArrays a) {
         bool sv = false;
         uint32_t x = 0;
         uint64_t cmax = 0;
+        int lev = 0;
         if (t < nA) {
             x = a.A[t];
             cmax = a.cost[x];
-            const int lev = level_of(st, cmax);
+            lev = level_of(st, cmax);
             atomicAdd(&a.cellAlev[(size_t)a.cell_of[x] * kLev + lev], 1u);
             atomicAdd(&a.ccellAlev[(size_t)a.coarse_of[x] * kLev + lev], 1u);
             if (a.blocked[x] != round) {
@@ -123,6 +124,20 @@ __global__ void __launch_bounds__(kBlock) rb_survive(RoundArrays a) {
         }
         const uint32_t p = wave_append(&st->nSurv, sv);
         if (sv) a.surv_list[p] = x;
+        // lowest survivor cost per key level (wave minimum, one atomic per wave and level)
+#pragma unroll
+        for (int j = 0; j < kLev; j++) {
+            uint64_t v = (sv && lev == j) ? cmax : ~0ull;
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) {
+                const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o, kWave);
+                const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o, kWave);
+                const uint64_t u = ((uint64_t)hi << 32) | lo;
+                v = u < v ? u : v;
+            }
+            if ((threadIdx.x & (kWave - 1)) == 0 && v != ~0ull)
+                atomicMin((unsigned long long*)&st->surv_min[j], (unsigned long long)v);
+        }
         // highest cost of A (wave maximum, one atomic per wave)
 #pragma unroll
         for (int o = kWave / 2; o > 0; o >>= 1) {
@@ -237,34 +252,50 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
         const uint32_t y = a.dg_y[t];
         const uint64_t tc = a.dg_tc[t], dlast = a.dg_dlast[t];
         const int32_t to = a.dg_to[t];
-        const int4 py = a.pts[y];
         const uint64_t cy = a.cost[y];
+        // key levels with a survivor that y could hold back: at or below
+        // the threshold's level, with some survivor cost <= min(cost y, threshold)
+        const int lth = level_of(st, tc);
+        const uint64_t cmin = cy < tc ? cy : tc;
+        uint32_t risk = 0;
+#pragma unroll
+        for (int j = 0; j < kLev; j++)
+            if (j <= lth && st->surv_min[j] <= cmin) risk |= 1u << j;
+        if (!risk) continue;
+        const int4 py = a.pts[y];
         const int32_t oy = py.w;
         // y's list: class and key of every entry
+        int lcls = 0, llev = kLev;
         if (lane < K) {
-            int cls = 0;
             uint64_t cc = 0;
             int32_t oo = 0;
             if (lane < a.cnt[y]) {
                 const uint32_t z = (uint32_t)a.nbr[(size_t)y * Kb + lane];
                 if (a.alive[z]) {
                     if (a.inA[z] == round) {
-                        cls = 2;
+                        lcls = 2;
                         cc = a.cost[z];
                         oo = a.pts[z].w;
+                        llev = level_of(st, cc);
                     } else {
-                        cls = 1;
+                        lcls = 1;
+                        llev = -1;
                     }
                 }
             }
-            s_ycls[w][lane] = cls;
+            s_ycls[w][lane] = lcls;
             s_yc[w][lane] = cc;
             s_yo[w][lane] = oo;
         }
         wave_sync_lds();
+        // a level whose survivors have k entries of y's list ranked below
+        // them (all within y's list radius) is safe
+#pragma unroll
+        for (int j = 0; j < kLev; j++)
+            if (__popcll(__ballot(lcls != 0 && llev < j)) >= k) risk &= ~(1u << j);
+        if (!risk) continue;
         const int ux = py.x - g.minx, uy = py.y - g.miny, uz = py.z - g.minz;
-        // R2[j] (0 = none found) for the key levels up to the threshold's
-        const int lth = level_of(st, tc);
+        // R2[j] (0 = none found) for the key levels at risk
         uint64_t R2[kLev];
         uint64_t rbox = 0;
         {
@@ -279,7 +310,7 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
                 if (r0[j] >= 0) {
                     const uint64_t e = (uint64_t)(r0[j] + 1) << l0.s;
                     R2[j] = 3 * e * e;
-                } else if (j <= lth && !cover0) {
+                } else if (((risk >> j) & 1u) && !cover0) {
                     need1 = true;
                 }
             }
@@ -296,7 +327,7 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
             const uint64_t cb = (cy < tc ? cy : tc) + 1;
 #pragma unroll
             for (int j = 0; j < kLev; j++) {
-                if (j > lth) continue;
+                if (!((risk >> j) & 1u)) continue;
                 if (R2[j] == 0) {
                     if (lane == 0) atomicMax((unsigned long long*)&st->glob_block[j], (unsigned long long)cb);
                 } else if (R2[j] > rbox) {
@@ -308,7 +339,7 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
             if (x == y || a.surv[x] != round) return;
             const uint64_t cx = a.cost[x];
             const int lx = level_of(st, cx);
-            if (lx > lth || R2[lx] == 0) return;  // above the threshold, or waiting on glob_block
+            if (!((risk >> lx) & 1u) || R2[lx] == 0) return;  // safe level, or waiting on glob_block
             const int4 px = a.pts[x];
             const uint64_t dxy = dist2(px.x, px.y, px.z, py.x, py.y, py.z);
             if (dxy < dlast || dxy >= R2[lx]) return;

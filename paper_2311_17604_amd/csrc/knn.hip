@@ -43,6 +43,8 @@ __global__ void __launch_bounds__(kBlock) knn_wave_k(GridView g, int k, int32_t*
                                                      int64_t* __restrict__ r2k) {
     __shared__ uint32_t lds[kBlock / kWave][2][kWave];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    // Waves stride over the queries in Morton order, so the waves resident
+    // at one time read overlapping cells.
     const uint32_t nw = gridDim.x * (kBlock / kWave);
     for (uint32_t q = blockIdx.x * (kBlock / kWave) + w; q < g.n; q += nw) {
         const int4 qp = g.pts[q];
@@ -86,7 +88,8 @@ int knn_all(Ctx* c, const GridView& g, int k, int K, KnnOut out, int64_t* fallba
     dim3 grid((g.n + kBlock - 1) / kBlock), block(kBlock);
     const char* mode = getenv("PDD_KNN_MODE");
     if (!(mode && mode[0] == 'l')) {
-        dim3 wg(std::min<uint32_t>((g.n + 3) / 4, 65536u));
+        const uint32_t nb = std::min<uint32_t>((g.n + 3) / 4, 16384u);
+        dim3 wg((nb + 7) / 8 * 8);
         switch (K) {
             case 8: hipLaunchKernelGGL(knn_wave_k<8>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
             case 16: hipLaunchKernelGGL(knn_wave_k<16>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;

@@ -23,6 +23,7 @@ struct RoundDev {
     int32_t top_orig, pad2;
     float frac;                   // share of alive points ranked this round (adapted)
     float frac_max;
+    uint64_t surv_min[kLev];      // lowest survivor cost per key level, this round
 };
 
 struct RoundArrays {
@@ -78,6 +79,36 @@ __device__ inline uint32_t wave_append(uint32_t* counter, bool pred) {
     if (m && lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
     base = __shfl(base, (int)leader, kWave);
     return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
+// Space for `cnt` items per thread of a kBlock-thread block: returns the
+// thread's first slot; one atomic on `counter` per block.  Every thread of
+// the block must call it.
+__device__ inline uint32_t block_reserve(uint32_t* counter, uint32_t cnt) {
+    constexpr int W = kBlock / kWave;
+    __shared__ uint32_t s_w[W + 1];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_up((int)incl, o, kWave);
+        if (lane >= o) incl += v;
+    }
+    if (lane == kWave - 1) s_w[wid] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int w = 0; w < W; w++) {
+            const uint32_t t = s_w[w];
+            s_w[w] = tot;
+            tot += t;
+        }
+        s_w[W] = tot ? atomicAdd(counter, tot) : 0u;
+    }
+    __syncthreads();
+    const uint32_t r = s_w[W] + s_w[wid] + incl - cnt;
+    __syncthreads();
+    return r;
 }
 
 // First-level bucket of a cost: 0 for 0, else (msb + 1) * 64 + next 6 bits.

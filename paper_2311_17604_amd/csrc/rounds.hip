@@ -78,6 +78,7 @@ __global__ void rb_begin(RoundArrays a) {
                 st->mode = 0;
                 st->top_cost = 0;
                 st->top_orig = 0x7FFFFFFF;
+                for (int j = 0; j < kLev; j++) st->surv_min[j] = ~0ull;
             }
         }
     }
@@ -176,23 +177,36 @@ __global__ void __launch_bounds__(kBlock) rb_collect0(RoundArrays a, int par) {
     if (st->done || st->err) return;
     const uint32_t na = st->n_alive, bsel = st->sel_bin, round = st->round, mode = st->mode;
     const uint32_t* L = a.alive_list[par];
-    const uint32_t n_it = (na + blockDim.x - 1) / blockDim.x * blockDim.x;
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_it; t += gridDim.x * blockDim.x) {
-        uint32_t i = 0, bb = 0;
-        const bool ok = t < na;
-        if (ok) {
-            i = L[t];
-            bb = bin0(a.cost[i]);
+    constexpr int IPT = 8;
+    for (uint32_t base = blockIdx.x * kBlock * IPT; base < na; base += gridDim.x * kBlock * IPT) {
+        uint32_t item[IPT];
+        uint32_t sel = 0, nsel = 0;
+#pragma unroll
+        for (int e = 0; e < IPT; e++) {
+            const uint32_t t = base + e * kBlock + threadIdx.x;
+            item[e] = 0;
+            if (t < na) {
+                const uint32_t i = L[t];
+                const uint32_t bb = bin0(a.cost[i]);
+                if (mode == 0 ? bb > bsel : bb == bsel) {
+                    item[e] = i;
+                    sel |= 1u << e;
+                    nsel++;
+                }
+            }
         }
-        const bool toA = ok && mode == 0 && bb > bsel;
-        const bool toC = ok && mode == 1 && bb == bsel;
-        const uint32_t pa = wave_append(&st->nA, toA);
-        const uint32_t pc = wave_append(&st->nCand, toC);
-        if (toA) {
-            a.A[pa] = i;
-            a.inA[i] = round;
+        uint32_t p = block_reserve(mode == 0 ? &st->nA : &st->nCand, nsel);
+#pragma unroll
+        for (int e = 0; e < IPT; e++) {
+            if (!((sel >> e) & 1u)) continue;
+            if (mode == 0) {
+                a.A[p] = item[e];
+                a.inA[item[e]] = round;
+            } else {
+                a.cand[0][p] = item[e];
+            }
+            p++;
         }
-        if (toC) a.cand[0][pc] = i;
     }
 }
 
@@ -448,16 +462,26 @@ __global__ void __launch_bounds__(kBlock) rb_compact(RoundArrays a, int par) {
     const uint32_t na = st->n_alive;
     const uint32_t* L = a.alive_list[par];
     uint32_t* M = a.alive_list[par ^ 1];
-    const uint32_t n_it = (na + blockDim.x - 1) / blockDim.x * blockDim.x;
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_it; t += gridDim.x * blockDim.x) {
-        uint32_t i = 0;
-        bool keep = false;
-        if (t < na) {
-            i = L[t];
-            keep = a.alive[i] != 0;
+    constexpr int IPT = 8;
+    for (uint32_t base = blockIdx.x * kBlock * IPT; base < na; base += gridDim.x * kBlock * IPT) {
+        uint32_t item[IPT];
+        uint32_t sel = 0, nsel = 0;
+#pragma unroll
+        for (int e = 0; e < IPT; e++) {
+            const uint32_t t = base + e * kBlock + threadIdx.x;
+            item[e] = 0;
+            if (t < na) {
+                item[e] = L[t];
+                if (a.alive[item[e]]) {
+                    sel |= 1u << e;
+                    nsel++;
+                }
+            }
         }
-        const uint32_t p = wave_append(&st->n_alive_new, keep);
-        if (keep) M[p] = i;
+        uint32_t p = block_reserve(&st->n_alive_new, nsel);
+#pragma unroll
+        for (int e = 0; e < IPT; e++)
+            if ((sel >> e) & 1u) M[p++] = item[e];
     }
 }
 
