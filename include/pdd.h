@@ -60,7 +60,8 @@ typedef struct {
     int32_t k;              /* neighbours in the cost, 1..32 (no default: required) */
     int32_t b;              /* extra buffered neighbours, k + b <= 32 (default: 8, capped) */
     int32_t voxel_log2;     /* cell edge = 2^voxel_log2 mm, 2..20 (default: chosen from density) */
-    float round_frac;       /* share of alive points ranked per removal round, (0, 1] (default 0.03) */
+    float round_frac;       /* initial share of alive points ranked per removal round, (0, 1] (default 0.01);
+                               adapted per round between 1e-5 and 4x the initial value */
     int32_t point_stride;   /* bytes between points: 12 or 16 (default 12) */
     int32_t flags;          /* PDD_F_* bits */
     int32_t reserved[4];

@@ -169,7 +169,7 @@ int pdd_decimate(pdd_ctx* ctx, const int32_t* d_xyz, int64_t n, int64_t keep_cou
     if (b < 0) return PDD_EINVAL;
     if (b == 0) b = (pdd::kMaxK - k) < 8 ? (pdd::kMaxK - k) : 8;
     if (k + b > pdd::kMaxK) return PDD_EINVAL;
-    float frac = opts->round_frac == 0.0f ? 0.03f : opts->round_frac;
+    float frac = opts->round_frac == 0.0f ? 0.01f : opts->round_frac;
     if (!(frac > 0.0f && frac <= 1.0f)) return PDD_EINVAL;
     const int stride = opts->point_stride == 0 ? 12 : opts->point_stride;
     if (stride != 12 && stride != 16) return PDD_EINVAL;

@@ -100,7 +100,28 @@ __global__ void __launch_bounds__(kBlock) rb_pair(RoundArrays a) {
     }
 }
 
-__global__ void __launch_bounds__(kBlock) rb_survive(RoundArrays a) {
+// x in A with at least k alive points of identical coordinates ranked below
+// it (same cost, larger original index) is removed this round whatever
+// happens around it: those points keep rho'(x) = 0 and rho(x | y) <= d2(x, y)
+// for every y.  Marks such x in gsafe.
+__global__ void __launch_bounds__(kBlock) rb_group(RoundArrays a) {
+    RoundDev* st = a.st;
+    if (st->done || st->err) return;
+    const uint32_t nA = st->nA, round = st->round;
+    const uint32_t k = (uint32_t)a.k;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nA; t += gridDim.x * blockDim.x) {
+        const uint32_t x = a.A[t];
+        const uint32_t lo = a.grp_lo[x], hi = a.grp_hi[x];
+        if (hi - lo <= k) continue;
+        const int32_t ox = a.pts[x].w;
+        uint32_t below = 0;
+        for (uint32_t z = lo; z < hi && below < k; z++)
+            if (z != x && a.alive[z] && a.pts[z].w > ox) below++;
+        if (below >= k) a.gsafe[x] = round;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) rb_survive(RoundArrays a, GridView g) {
     RoundDev* st = a.st;
     if (st->done || st->err) return;
     const uint32_t nA = st->nA, round = st->round;
@@ -114,12 +135,16 @@ __global__ void __launch_bounds__(kBlock) rb_survive(RoundArrays a) {
             x = a.A[t];
             cmax = a.cost[x];
             lev = level_of(st, cmax);
-            atomicAdd(&a.cellAlev[(size_t)a.cell_of[x] * kLev + lev], 1u);
-            atomicAdd(&a.ccellAlev[(size_t)a.coarse_of[x] * kLev + lev], 1u);
-            if (a.blocked[x] != round) {
+            const uint32_t c0 = a.of0[x];
+            uint32_t c = c0;
+            for (int L = 0; L < g.nlev; L++) {
+                atomicAdd(&a.cellAlev[(size_t)(g.lv[L].base + c) * kLev + lev], 1u);
+                if (L + 1 < g.nlev) c = g.lv[L].parent[c];
+            }
+            if (a.blocked[x] != round && a.gsafe[x] != round) {
                 sv = true;
                 a.surv[x] = round;
-                atomicAdd(&a.ccS[a.coarse_of[x]], 1u);
+                atomicAdd(&a.cS[c0], 1u);
             }
         }
         const uint32_t p = wave_append(&st->nSurv, sv);
@@ -151,85 +176,101 @@ __global__ void __launch_bounds__(kBlock) rb_survive(RoundArrays a) {
     }
 }
 
-// Groups the survivors by coarse cell (offsets from the scan of ccS); takes
-// ccS back to zero on the way.
+// Groups the survivors by level-0 cell (offsets from the scan of cS), so
+// that the survivors of any cell of any level are one run of surv_bucket;
+// takes cS back to zero on the way.
 __global__ void __launch_bounds__(kBlock) rb_bucket(RoundArrays a) {
     RoundDev* st = a.st;
     if (st->done || st->err) return;
     const uint32_t ns = st->nSurv;
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ns; t += gridDim.x * blockDim.x) {
         const uint32_t x = a.surv_list[t];
-        const uint32_t cc = a.coarse_of[x];
-        const uint32_t slot = a.surv_off[cc] + atomicSub(&a.ccS[cc], 1u) - 1u;
-        a.surv_bucket[slot] = x;
-        // the highest key survives every condition; find its index
+        const uint32_t c = a.of0[x];
+        a.surv_bucket[a.surv_off[c] + atomicSub(&a.cS[c], 1u) - 1u] = x;
+    }
+    // the highest key of A survives every condition; find its index
+    const uint32_t nA = st->nA;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nA; t += gridDim.x * blockDim.x) {
+        const uint32_t x = a.A[t];
         if (a.cost[x] == st->top_cost) atomicMin(&st->top_orig, a.pts[x].w);
     }
 }
 
-// For each key level j: the first Chebyshev ring r <= RMAX around cell
-// (cx, cy, cz) of a grid level whose block holds at least k alive points
-// ranked below level j (outside A, or in A at a lower level), from per-cell
-// counts; -1 if none.  *cover: the block of radius RMAX covers the grid.
-template <int RMAX>
-__device__ void ring_levels(const LevelView& lv, int cx, int cy, int cz, const uint32_t* alive_cnt,
-                            const uint32_t* alev, int k, int* rj, bool* cover) {
+// Largest squared distance from relative coordinate u to an integer point of
+// cells [c - r, c + r] (edge 2^s) along one axis.
+__device__ inline uint64_t block_reach2(int u, int c, int r, int s) {
+    const int lo = (c - r) << s, hi = ((c + r + 1) << s) - 1;
+    const uint64_t m = (uint64_t)max(u - lo, hi - u);
+    return m * m;
+}
+
+// For each key level j in `want`, an upper bound R2[j] on the squared
+// distance from y (relative coordinates u) to its k-th nearest alive point
+// ranked below level j (outside A, or in A at a lower level): the reach of
+// the first block, over shells 0 and 1 of the levels from L1 up, whose cells
+// hold k such points by the per-cell counts.  0 where even the top block
+// (the whole cloud) holds fewer.
+__device__ void level_bounds(const GridView& g, const RoundArrays& a, int ux, int uy, int uz, int L1, uint32_t want,
+                             int k, uint64_t* R2) {
     const int lane = (int)lane_id();
-    constexpr int side = 2 * RMAX + 1, ncube = side * side * side;
-    uint32_t acc[RMAX + 1][kLev];
 #pragma unroll
-    for (int r = 0; r <= RMAX; r++)
+    for (int j = 0; j < kLev; j++) R2[j] = 0;
+    for (int L = L1; L < g.nlev && want; L++) {
+        const LevelView& lv = g.lv[L];
+        const int s = lv.s;
+        const int cx = ux >> s, cy = uy >> s, cz = uz >> s;
+        uint32_t b1[kLev];
 #pragma unroll
-        for (int j = 0; j < kLev; j++) acc[r][j] = 0;
-    for (int base = 0; base < ncube; base += kWave) {
-        const int idx = base + lane;
-        if (idx < ncube) {
-            const int dz = idx / (side * side) - RMAX;
-            const int rem = idx % (side * side);
-            const int dy = rem / side - RMAX, dx = rem % side - RMAX;
-            const int x = cx + dx, y = cy + dy, z = cz + dz;
+        for (int j = 0; j < kLev; j++) b1[j] = 0;
+        if (lane < 27) {
+            const int x = cx + lane % 3 - 1, y = cy + (lane / 3) % 3 - 1, z = cz + lane / 9 - 1;
             if (x >= 0 && y >= 0 && z >= 0 && x <= lv.cmax[0] && y <= lv.cmax[1] && z <= lv.cmax[2]) {
                 const uint32_t c =
                     hash_find(lv.hkeys, lv.hvals, lv.hmask, morton3((uint32_t)x, (uint32_t)y, (uint32_t)z));
                 if (c != kNone) {
-                    const int ring = max(abs(dx), max(abs(dy), abs(dz)));
+                    const size_t gc = lv.base + c;
                     uint32_t la[kLev], inA = 0;
 #pragma unroll
                     for (int j = 0; j < kLev; j++) {
-                        la[j] = alev[(size_t)c * kLev + j];
+                        la[j] = a.cellAlev[gc * kLev + j];
                         inA += la[j];
                     }
-                    uint32_t below = alive_cnt[c] - inA;
+                    uint32_t below = a.cell_alive[gc] - inA;
 #pragma unroll
                     for (int j = 0; j < kLev; j++) {
-#pragma unroll
-                        for (int r = 0; r <= RMAX; r++)
-                            if (ring <= r) acc[r][j] += below;
+                        b1[j] = below;
                         below += la[j];
                     }
                 }
             }
         }
-    }
-#pragma unroll
-    for (int j = 0; j < kLev; j++) rj[j] = -1;
-#pragma unroll
-    for (int r = RMAX; r >= 0; r--)
 #pragma unroll
         for (int j = 0; j < kLev; j++) {
-            uint32_t v = acc[r][j];
+            if (!((want >> j) & 1u)) continue;
+            const uint32_t own = (uint32_t)__builtin_amdgcn_readlane((int)b1[j], 13);
+            uint32_t v = b1[j];
 #pragma unroll
             for (int o = kWave / 2; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, kWave);
-            if (v >= (uint32_t)k) rj[j] = r;
+            if (own >= (uint32_t)k) {
+                R2[j] = block_reach2(ux, cx, 0, s) + block_reach2(uy, cy, 0, s) + block_reach2(uz, cz, 0, s);
+                want &= ~(1u << j);
+            } else if (v >= (uint32_t)k) {
+                R2[j] = block_reach2(ux, cx, 1, s) + block_reach2(uy, cy, 1, s) + block_reach2(uz, cz, 1, s);
+                want &= ~(1u << j);
+            }
         }
-    *cover = cx - RMAX <= 0 && cy - RMAX <= 0 && cz - RMAX <= 0 && cx + RMAX >= lv.cmax[0] &&
-             cy + RMAX >= lv.cmax[1] && cz + RMAX >= lv.cmax[2];
+    }
+}
+
+// Distance along one axis from coordinate u to cell index c of size 2^s.
+__device__ inline uint64_t axis_gap(int u, int c, int s) {
+    const int lo = c << s, hi = ((c + 1) << s) - 1;
+    return (uint64_t)(u < lo ? lo - u : (u > hi ? u - hi : 0));
 }
 
 // A dangerous y may hold a surviving lower x beyond its list within
 // rho(x | y) only if key(x) <= its threshold.  For x of key level j,
-// rho(x | y) is below R_j, the radius of the smallest cell block around y
-// with k alive points ranked below level j.  Such an x stays unless a count
+// rho(x | y) is at most R_j (level_bounds).  Such an x stays unless a count
 // of alive points not above x within d(x, y) of y reaches k: the entries of
 // y's list not above x, plus entries of x's own list that lie beyond y's
 // list radius and within d(x, y).  When no R_j is found, every survivor of
@@ -295,35 +336,17 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
             if (__popcll(__ballot(lcls != 0 && llev < j)) >= k) risk &= ~(1u << j);
         if (!risk) continue;
         const int ux = py.x - g.minx, uy = py.y - g.miny, uz = py.z - g.minz;
-        // R2[j] (0 = none found) for the key levels at risk
+        // R2[j] (0 = none found) for the key levels at risk, from the finest
+        // level whose 3x3x3 block can reach beyond y's list radius (the
+        // list holds every alive point nearer than dlast, fewer than k of
+        // them below a risky level)
         uint64_t R2[kLev];
         uint64_t rbox = 0;
         {
-            int r0[kLev], r1[kLev];
-            bool cover0, cover1;
-            const LevelView& l0 = g.lv[0];
-            ring_levels<2>(l0, ux >> l0.s, uy >> l0.s, uz >> l0.s, a.cell_alive, a.cellAlev, k, r0, &cover0);
-            bool need1 = false;
-#pragma unroll
-            for (int j = 0; j < kLev; j++) {
-                R2[j] = 0;
-                if (r0[j] >= 0) {
-                    const uint64_t e = (uint64_t)(r0[j] + 1) << l0.s;
-                    R2[j] = 3 * e * e;
-                } else if (((risk >> j) & 1u) && !cover0) {
-                    need1 = true;
-                }
-            }
-            if (need1) {
-                const LevelView& l1 = g.lv[1];
-                ring_levels<6>(l1, ux >> l1.s, uy >> l1.s, uz >> l1.s, a.ccell_alive, a.ccellAlev, k, r1, &cover1);
-#pragma unroll
-                for (int j = 0; j < kLev; j++)
-                    if (R2[j] == 0 && r1[j] >= 0) {
-                        const uint64_t e = (uint64_t)(r1[j] + 1) << l1.s;
-                        R2[j] = 3 * e * e;
-                    }
-            }
+            int sneed = 0;
+            while (sneed < 21 && (12ull << (2 * sneed)) < dlast) sneed++;
+            const int L1 = min(max(sneed - g.lv[0].s, 0), g.nlev - 1);
+            level_bounds(g, a, ux, uy, uz, L1, risk, k, R2);
             const uint64_t cb = (cy < tc ? cy : tc) + 1;
 #pragma unroll
             for (int j = 0; j < kLev; j++) {
@@ -336,7 +359,7 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
             }
         }
         auto consider = [&](uint32_t x) {
-            if (x == y || a.surv[x] != round) return;
+            if (x == y || a.surv[x] != round || a.blocked[x] == round) return;  // (gsafe points are not survivors)
             const uint64_t cx = a.cost[x];
             const int lx = level_of(st, cx);
             if (!((risk >> lx) & 1u) || R2[lx] == 0) return;  // safe level, or waiting on glob_block
@@ -365,12 +388,19 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
         };
         (void)ns;
         if (rbox != 0) {
-            const LevelView& l1 = g.lv[1];
-            const int sc = l1.s;
+            // survivors within sqrt(rbox) of y, from the cells of the level
+            // where the box spans at most 4 cells per axis; the survivors of
+            // a cell are the run of the bucket array between the offsets of
+            // its first level-0 cell and the next cell's
             const int ri = (int)sqrt((double)rbox) + 1;
-            const int x0 = max((ux - ri) >> sc, 0), x1 = min((ux + ri) >> sc, l1.cmax[0]);
-            const int y0 = max((uy - ri) >> sc, 0), y1 = min((uy + ri) >> sc, l1.cmax[1]);
-            const int z0 = max((uz - ri) >> sc, 0), z1 = min((uz + ri) >> sc, l1.cmax[2]);
+            int se = 0;
+            while (se < 21 && (3 << se) < 2 * ri) se++;
+            const int Le = min(max(se - g.lv[0].s, 0), g.nlev - 1);
+            const LevelView& lv = g.lv[Le];
+            const int sc = lv.s;
+            const int x0 = max((ux - ri) >> sc, 0), x1 = min((ux + ri) >> sc, lv.cmax[0]);
+            const int y0 = max((uy - ri) >> sc, 0), y1 = min((uy + ri) >> sc, lv.cmax[1]);
+            const int z0 = max((uz - ri) >> sc, 0), z1 = min((uz + ri) >> sc, lv.cmax[2]);
             const int nx = x1 - x0 + 1, nyy = y1 - y0 + 1, nz = z1 - z0 + 1;
             const int nbox = nx * nyy * nz;
             for (int base = 0; base < nbox; base += kWave) {
@@ -378,11 +408,17 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
                 uint32_t st0 = 0, cnt = 0;
                 if (idx < nbox) {
                     const int xx = x0 + idx % nx, yy = y0 + (idx / nx) % nyy, zz = z0 + idx / (nx * nyy);
-                    const uint32_t c =
-                        hash_find(l1.hkeys, l1.hvals, l1.hmask, morton3((uint32_t)xx, (uint32_t)yy, (uint32_t)zz));
-                    if (c != kNone) {
-                        st0 = a.surv_off[c];
-                        cnt = a.surv_off[c + 1] - st0;
+                    // skip cells wholly at squared distance >= rbox
+                    const uint64_t gx = axis_gap(ux, xx, sc), gy = axis_gap(uy, yy, sc), gz = axis_gap(uz, zz, sc);
+                    if (gx * gx + gy * gy + gz * gz < rbox) {
+                        const uint32_t c = hash_find(lv.hkeys, lv.hvals, lv.hmask,
+                                                     morton3((uint32_t)xx, (uint32_t)yy, (uint32_t)zz));
+                        if (c != kNone) {
+                            const uint32_t f0 = lv.first0 ? lv.first0[c] : c;
+                            const uint32_t f1 = lv.first0 ? lv.first0[c + 1] : c + 1;
+                            st0 = a.surv_off[f0];
+                            cnt = a.surv_off[f1] - st0;
+                        }
                     }
                 }
                 uint32_t incl = cnt;
@@ -393,6 +429,7 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
                 }
                 const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
                 if (total == 0) continue;
+                if (lane == 0) atomicAdd(&st->work, total);
                 s_start[w][lane] = st0;
                 s_excl[w][lane] = incl - cnt;
                 wave_sync_lds();
@@ -417,10 +454,11 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
 template <int K>
 int launch_k(Ctx* c, const RoundArrays& a, const GridView& g) {
     const unsigned G = 1024;
+    hipLaunchKernelGGL(rb_group, dim3(G), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_pair<K>, dim3(G), dim3(kBlock), 0, c->stream, a);
-    hipLaunchKernelGGL(rb_survive, dim3(G), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(rb_survive, dim3(G), dim3(kBlock), 0, c->stream, a, g);
     PDD_HIP(c, hipGetLastError());
-    int rc = exclusive_scan_u32(c, a.ccS, a.surv_off, a.nccells + 1, nullptr);
+    int rc = exclusive_scan_u32(c, a.cS, a.surv_off, a.ncells0 + 1, nullptr);
     if (rc) return rc;
     hipLaunchKernelGGL(rb_bucket, dim3(G), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_danger<K>, dim3(G), dim3(kBlock), 0, c->stream, a, g);

@@ -85,37 +85,52 @@ __device__ inline uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __b
 // device views
 // ---------------------------------------------------------------------------
 
-constexpr int kMaxLevels = 8;
+constexpr int kMaxLevels = 22;
 
 // Cells of one level: cubes of edge 2^s mm, i.e. runs of equal Morton code
-// >> 3s in the sorted points.
+// >> 3s in the sorted points.  Level l has s = s0 + l: each cell is the union
+// of the (at most 8) cells below it, and its descendants at every finer
+// level are a contiguous run of that level's cells.
 struct LevelView {
     const uint32_t* start;    // [ncells + 1] first sorted point of each cell
     const uint64_t* hkeys;    // [hmask + 1] Morton cell codes (kEmptyKey = empty slot)
     const uint32_t* hvals;    // [hmask + 1] cell index
-    const uint32_t* of;       // [n] cell of each sorted point (levels 0 and 1 only)
+    const uint32_t* parent;   // [ncells] cell one level up (nullptr at the top level)
+    const uint32_t* first0;   // [ncells + 1] first level-0 cell inside each cell (level 0: nullptr)
     uint32_t hmask;
     uint32_t ncells;
+    uint32_t base;            // index of the level's first cell in the numbering of all levels' cells
     int32_t cmax[3];          // largest cell coordinate per axis
     int32_t s;
+    int32_t pad;
 };
 
 // The grid: points in Morton order with their original index, and a stack
-// of cell levels with edges 2^s, 2^(s+3), ... up to one covering the cloud.
+// of cell levels with edges 2^s0, 2^(s0+1), ... up to one whose 3x3x3 block
+// covers the cloud.
 struct GridView {
     const int4* pts;          // [n] x, y, z, original index
+    const uint32_t* of0;      // [n] level-0 cell of each sorted point
     uint32_t n;
+    uint32_t total_cells;     // cells over all levels
     int32_t minx, miny, minz;
     int32_t nlev;             // >= 2
     LevelView lv[kMaxLevels];
 };
+
+// level-l cell of a level-0 cell
+__device__ inline uint32_t cell_up(const GridView& g, uint32_t c0, int l) {
+    for (int i = 0; i < l; i++) c0 = g.lv[i].parent[c0];
+    return c0;
+}
 
 struct Level {
     uint32_t* start = nullptr;
     uint64_t* key = nullptr;
     uint64_t* hkeys = nullptr;
     uint32_t* hvals = nullptr;
-    uint32_t* of = nullptr;
+    uint32_t* parent = nullptr;
+    uint32_t* first0 = nullptr;
     uint64_t hcap = 0;
     uint32_t ncells = 0;
 };
@@ -123,6 +138,7 @@ struct Level {
 struct Grid {
     GridView v;
     int4* pts = nullptr;
+    uint32_t* of0 = nullptr;
     Level lev[kMaxLevels];
 };
 

@@ -64,25 +64,6 @@ __global__ void __launch_bounds__(kBlock) permute_k(const int32_t* __restrict__ 
     }
 }
 
-// lev_hist[L] += 1 for each sorted neighbour pair whose codes first differ at
-// level L (bit position / 3): that pair is a cell boundary for every s <= L.
-__global__ void __launch_bounds__(kBlock) level_hist_k(const uint64_t* __restrict__ keys, uint32_t n,
-                                                       uint32_t* __restrict__ lev_hist) {
-    __shared__ uint32_t h[22];
-    if (threadIdx.x < 22) h[threadIdx.x] = 0;
-    __syncthreads();
-    for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x + 1; j < n; j += (size_t)gridDim.x * blockDim.x) {
-        uint64_t x = keys[j] ^ keys[j - 1];
-        if (x) atomicAdd(&h[(63 - __clzll(x)) / 3], 1u);
-    }
-    __syncthreads();
-    if (threadIdx.x < 22 && h[threadIdx.x]) atomicAdd(&lev_hist[threadIdx.x], h[threadIdx.x]);
-}
-
-__global__ void zero22(uint32_t* p) {
-    if (threadIdx.x < 22) p[threadIdx.x] = 0;
-}
-
 __global__ void __launch_bounds__(kBlock) cell_flag_k(const uint64_t* __restrict__ keys, uint32_t n, int s,
                                                       uint32_t* __restrict__ flag) {
     for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (size_t)gridDim.x * blockDim.x)
@@ -95,13 +76,72 @@ __global__ void __launch_bounds__(kBlock) cell_write_k(const uint64_t* __restric
                                                        uint64_t* __restrict__ ckey, uint32_t ncells,
                                                        uint32_t* __restrict__ of) {
     for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (size_t)gridDim.x * blockDim.x) {
-        if (of) of[j] = pos[j] + flag[j] - 1u;
+        of[j] = pos[j] + flag[j] - 1u;
         if (flag[j]) {
             uint32_t c = pos[j];
             start[c] = (uint32_t)j;
             ckey[c] = keys[j] >> (3 * s);
         }
         if (j == 0) start[ncells] = n;
+    }
+}
+
+// Level l+1 from level l: a new cell starts where the parent code
+// (cell code >> 3) changes.
+__global__ void __launch_bounds__(kBlock) up_flag_k(const uint64_t* __restrict__ key, uint32_t nc,
+                                                    uint32_t* __restrict__ flag) {
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (size_t)gridDim.x * blockDim.x)
+        flag[c] = (c == 0 || (key[c] >> 3) != (key[c - 1] >> 3)) ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(kBlock) up_write_k(const uint64_t* __restrict__ key, const uint32_t* __restrict__ start,
+                                                     const uint32_t* __restrict__ first0, uint32_t nc, uint32_t n,
+                                                     uint32_t nc0, const uint32_t* __restrict__ flag,
+                                                     const uint32_t* __restrict__ pos, uint32_t* __restrict__ parent,
+                                                     uint32_t* __restrict__ ustart, uint64_t* __restrict__ ukey,
+                                                     uint32_t* __restrict__ ufirst0, uint32_t unc) {
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (size_t)gridDim.x * blockDim.x) {
+        parent[c] = pos[c] + flag[c] - 1u;
+        if (flag[c]) {
+            const uint32_t u = pos[c];
+            ustart[u] = start[c];
+            ukey[u] = key[c] >> 3;
+            ufirst0[u] = first0 ? first0[c] : (uint32_t)c;
+        }
+        if (c == 0) {
+            ustart[unc] = n;
+            ufirst0[unc] = nc0;
+        }
+    }
+}
+
+// Occupancy sample for the choice of the finest level: for `ns` points
+// spread evenly over the sorted order and every s in [0, 21], the number of
+// points sharing the point's cell of edge 2^s, binned by floor(log2) into
+// hist[s * 32 + bin].
+__global__ void __launch_bounds__(kBlock) occ_sample_k(const uint64_t* __restrict__ keys, uint32_t n, uint32_t ns,
+                                                       uint32_t* __restrict__ hist) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns) return;
+    const uint32_t j = (uint32_t)((uint64_t)i * n / ns);
+    const uint64_t key = keys[j];
+    for (int s = 0; s < 22; s++) {
+        const uint64_t p = key >> (3 * s);
+        // first index with prefix >= p, first index with prefix > p
+        uint32_t lo = 0, hi = j;
+        while (lo < hi) {
+            const uint32_t m = (lo + hi) >> 1;
+            if ((keys[m] >> (3 * s)) < p) lo = m + 1; else hi = m;
+        }
+        const uint32_t b = lo;
+        lo = j + 1;
+        hi = n;
+        while (lo < hi) {
+            const uint32_t m = (lo + hi) >> 1;
+            if ((keys[m] >> (3 * s)) <= p) lo = m + 1; else hi = m;
+        }
+        const uint32_t cnt = lo - b;
+        atomicAdd(&hist[s * 32 + (31 - __clz(cnt))], 1u);
     }
 }
 
@@ -135,7 +175,7 @@ inline unsigned grid_for(size_t count, unsigned maxg = 16384) {
 }
 
 // scratch slots used while building a grid
-enum { kSlotBounds = 0, kSlotKeys = 1, kSlotVals = 2, kSlotFlag = 3, kSlotPos = 4, kSlotLev = 5 };
+enum { kSlotBounds = 0, kSlotKeys = 1, kSlotVals = 2, kSlotFlag = 3, kSlotPos = 4, kSlotLev = 5, kSlotOcc = 6 };
 
 }  // namespace
 
@@ -144,48 +184,16 @@ static void free_level(Level* l) {
     if (l->key) (void)hipFree(l->key);
     if (l->hkeys) (void)hipFree(l->hkeys);
     if (l->hvals) (void)hipFree(l->hvals);
-    if (l->of) (void)hipFree(l->of);
+    if (l->parent) (void)hipFree(l->parent);
+    if (l->first0) (void)hipFree(l->first0);
     *l = Level();
 }
 
 void free_grid(Grid* g) {
     if (g->pts) (void)hipFree(g->pts);
+    if (g->of0) (void)hipFree(g->of0);
     for (auto& l : g->lev) free_level(&l);
     *g = Grid();
-}
-
-static int alloc_dev(Ctx* c, void** p, size_t bytes);
-
-// Cells at level s: runs of equal code >> 3s in the sorted keys, their
-// starts, a hash table from cell code to cell index, and the cell of every
-// sorted point.
-static int build_level(Ctx* c, const uint64_t* sk, uint32_t n, int s, uint32_t* flag, uint32_t* pos, Level* l,
-                       bool with_of) {
-    int rc;
-    hipLaunchKernelGGL(cell_flag_k, dim3(grid_for(n)), dim3(kBlock), 0, c->stream, sk, n, s, flag);
-    PDD_HIP(c, hipGetLastError());
-    if ((rc = exclusive_scan_u32(c, flag, pos, n, pos + n))) return rc;
-    uint32_t* hn = (uint32_t*)c->pinned;
-    PDD_HIP(c, hipMemcpyAsync(hn, pos + n, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
-    PDD_HIP(c, hipStreamSynchronize(c->stream));
-    const uint32_t ncells = hn[0];
-    l->ncells = ncells;
-    if ((rc = alloc_dev(c, (void**)&l->start, (size_t)(ncells + 1) * 4))) return rc;
-    if ((rc = alloc_dev(c, (void**)&l->key, (size_t)ncells * 8))) return rc;
-    if (with_of && (rc = alloc_dev(c, (void**)&l->of, (size_t)n * 4))) return rc;
-    hipLaunchKernelGGL(cell_write_k, dim3(grid_for(n)), dim3(kBlock), 0, c->stream, sk, n, s, flag, pos, l->start,
-                       l->key, ncells, l->of);
-    PDD_HIP(c, hipGetLastError());
-    uint64_t cap = 1024;
-    while (cap < 2ull * ncells) cap <<= 1;
-    if ((rc = alloc_dev(c, (void**)&l->hkeys, cap * 8))) return rc;
-    if ((rc = alloc_dev(c, (void**)&l->hvals, cap * 4))) return rc;
-    l->hcap = cap;
-    hipLaunchKernelGGL(hash_clear_k, dim3(grid_for(cap)), dim3(kBlock), 0, c->stream, l->hkeys, cap);
-    hipLaunchKernelGGL(hash_insert_k, dim3(grid_for(ncells)), dim3(kBlock), 0, c->stream, l->key, ncells, l->hkeys,
-                       l->hvals, (uint32_t)(cap - 1));
-    PDD_HIP(c, hipGetLastError());
-    return PDD_OK;
 }
 
 static int alloc_dev(Ctx* c, void** p, size_t bytes) {
@@ -199,18 +207,62 @@ static int alloc_dev(Ctx* c, void** p, size_t bytes) {
     return PDD_OK;
 }
 
-// Chooses the voxel so that a cell holds about `target` points on average.
-static int choose_level(const uint32_t* lev_hist, uint32_t n, int min_s, int max_s, double target) {
-    int best = min_s;
-    double bestd = 1e300;
-    for (int s = min_s; s <= max_s; s++) {
-        uint64_t cells = 1;
-        for (int L = s; L < 22; L++) cells += lev_hist[L];
-        double occ = (double)n / (double)cells;
-        double d = occ > target ? occ / target : target / occ;
-        if (d < bestd) { bestd = d; best = s; }
+// number of cells (the scan total), read back
+static int read_count(Ctx* c, const uint32_t* dev, uint32_t* out) {
+    uint32_t* h = (uint32_t*)c->pinned;
+    PDD_HIP(c, hipMemcpyAsync(h, dev, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    PDD_HIP(c, hipStreamSynchronize(c->stream));
+    *out = h[0];
+    return PDD_OK;
+}
+
+// hash table from cell code to cell index, capacity >= 2 * ncells
+static int build_hash(Ctx* c, Level* l) {
+    int rc;
+    uint64_t cap = 1024;
+    while (cap < 2ull * l->ncells) cap <<= 1;
+    if ((rc = alloc_dev(c, (void**)&l->hkeys, cap * 8))) return rc;
+    if ((rc = alloc_dev(c, (void**)&l->hvals, cap * 4))) return rc;
+    l->hcap = cap;
+    hipLaunchKernelGGL(hash_clear_k, dim3(grid_for(cap)), dim3(kBlock), 0, c->stream, l->hkeys, cap);
+    hipLaunchKernelGGL(hash_insert_k, dim3(grid_for(l->ncells)), dim3(kBlock), 0, c->stream, l->key, l->ncells,
+                       l->hkeys, l->hvals, (uint32_t)(cap - 1));
+    PDD_HIP(c, hipGetLastError());
+    return PDD_OK;
+}
+
+// The finest level: the largest s whose cells hold fewer than 32 points for 90%
+// of the points (occupancy seen from the points, which is what a search
+// pays), so that the densest regions still get small cells; coarser regions
+// use the levels above.
+static int choose_finest(Ctx* c, const uint64_t* sk, uint32_t n, int* s_out) {
+    uint32_t* hist = (uint32_t*)scratch(c, kSlotOcc, 22 * 32 * 4);
+    if (!hist) return PDD_ENOMEM;
+    int rc;
+    if ((rc = fill_u32(c, hist, 0, 22 * 32))) return rc;
+    const uint32_t ns = n < 4096 ? n : 4096;
+    hipLaunchKernelGGL(occ_sample_k, dim3((ns + kBlock - 1) / kBlock), dim3(kBlock), 0, c->stream, sk, n, ns, hist);
+    PDD_HIP(c, hipGetLastError());
+    uint32_t* h = (uint32_t*)c->pinned;
+    PDD_HIP(c, hipMemcpyAsync(h, hist, 22 * 32 * 4, hipMemcpyDeviceToHost, c->stream));
+    PDD_HIP(c, hipStreamSynchronize(c->stream));
+    int best = 0;
+    for (int s = 0; s < 22; s++) {
+        // 90th percentile bin of the counts
+        uint32_t acc = 0;
+        int p90 = 31;
+        for (int b = 0; b < 32; b++) {
+            acc += h[s * 32 + b];
+            if ((uint64_t)acc * 10 >= (uint64_t)ns * 9) {
+                p90 = b;
+                break;
+            }
+        }
+        if (p90 <= 4) best = s;  // counts below 32
+        else break;
     }
-    return best;
+    *s_out = best > 16 ? 16 : best;
+    return PDD_OK;
 }
 
 int build_grid(Ctx* c, const int32_t* xyz, int64_t n64, int stride, int voxel_log2, Grid* g) {
@@ -224,8 +276,7 @@ int build_grid(Ctx* c, const int32_t* xyz, int64_t n64, int stride, int voxel_lo
     uint32_t* vals = (uint32_t*)scratch(c, kSlotVals, (size_t)n * 4);
     uint32_t* flag = (uint32_t*)scratch(c, kSlotFlag, (size_t)n * 4);
     uint32_t* pos = (uint32_t*)scratch(c, kSlotPos, (size_t)(n + 1) * 4);
-    uint32_t* lev = (uint32_t*)scratch(c, kSlotLev, 32 * 4);
-    if (!bnd || !keys || !vals || !flag || !pos || !lev) return PDD_ENOMEM;
+    if (!bnd || !keys || !vals || !flag || !pos) return PDD_ENOMEM;
     int32_t* hb = (int32_t*)c->pinned;
 
     hipLaunchKernelGGL(bounds_init, dim3(1), dim3(64), 0, c->stream, bnd);
@@ -256,18 +307,8 @@ int build_grid(Ctx* c, const int32_t* xyz, int64_t n64, int stride, int voxel_lo
     hipLaunchKernelGGL(permute_k, dim3(grid_for(n)), dim3(kBlock), 0, c->stream, xyz, sw, sv, n, g->pts);
     PDD_HIP(c, hipGetLastError());
 
-    int s = voxel_log2;
-    if (s == 0) {
-        hipLaunchKernelGGL(zero22, dim3(1), dim3(64), 0, c->stream, lev);
-        hipLaunchKernelGGL(level_hist_k, dim3(grid_for(n, 2048)), dim3(kBlock), 0, c->stream, sk, n, lev);
-        PDD_HIP(c, hipGetLastError());
-        uint32_t* hl = (uint32_t*)c->pinned;
-        PDD_HIP(c, hipMemcpyAsync(hl, lev, 22 * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
-        PDD_HIP(c, hipStreamSynchronize(c->stream));
-        uint32_t lh[22];
-        for (int i = 0; i < 22; i++) lh[i] = hl[i];
-        s = choose_level(lh, n, 4, 12, 4.0);
-    }
+    int s0 = voxel_log2;
+    if (s0 == 0 && (rc = choose_finest(c, sk, n, &s0))) return rc;
 
     GridView& v = g->v;
     v.pts = g->pts;
@@ -275,29 +316,67 @@ int build_grid(Ctx* c, const int32_t* xyz, int64_t n64, int stride, int voxel_lo
     v.minx = mn[0];
     v.miny = mn[1];
     v.minz = mn[2];
-    // levels s, s+3, ... until one cell per axis covers the cloud (at least two)
-    int nlev = 0;
-    for (int sl = s;; sl += 3) {
-        if (sl > 21) sl = 21;
-        Level* l = &g->lev[nlev];
-        if ((rc = build_level(c, sk, n, sl, flag, pos, l, nlev < 2))) return rc;
-        LevelView& lv = v.lv[nlev];
-        lv.start = l->start;
-        lv.hkeys = l->hkeys;
-        lv.hvals = l->hvals;
-        lv.of = l->of;
-        lv.hmask = (uint32_t)(l->hcap - 1);
-        lv.ncells = l->ncells;
-        lv.s = sl;
+
+    // level 0 from the sorted point codes
+    Level* l0 = &g->lev[0];
+    hipLaunchKernelGGL(cell_flag_k, dim3(grid_for(n)), dim3(kBlock), 0, c->stream, sk, n, s0, flag);
+    PDD_HIP(c, hipGetLastError());
+    if ((rc = exclusive_scan_u32(c, flag, pos, n, pos + n))) return rc;
+    if ((rc = read_count(c, pos + n, &l0->ncells))) return rc;
+    if ((rc = alloc_dev(c, (void**)&l0->start, (size_t)(l0->ncells + 1) * 4))) return rc;
+    if ((rc = alloc_dev(c, (void**)&l0->key, (size_t)l0->ncells * 8))) return rc;
+    if ((rc = alloc_dev(c, (void**)&g->of0, (size_t)n * 4))) return rc;
+    hipLaunchKernelGGL(cell_write_k, dim3(grid_for(n)), dim3(kBlock), 0, c->stream, sk, n, s0, flag, pos, l0->start,
+                       l0->key, l0->ncells, g->of0);
+    PDD_HIP(c, hipGetLastError());
+    if ((rc = build_hash(c, l0))) return rc;
+    v.of0 = g->of0;
+
+    // coarser levels from the cells below, until the 3x3x3 block around any
+    // cell covers the cloud (cmax <= 1 per axis), at least two levels
+    int nlev = 1;
+    uint32_t total = l0->ncells;
+    for (int l = 0;; l++) {
+        const int sl = s0 + l;
+        LevelView& lv = v.lv[l];
+        Level* L = &g->lev[l];
         bool top = true;
         for (int a = 0; a < 3; a++) {
             lv.cmax[a] = (int32_t)(((int64_t)mx[a] - mn[a]) >> sl);
             if (lv.cmax[a] > 1) top = false;
         }
-        nlev++;
+        lv.start = L->start;
+        lv.hkeys = L->hkeys;
+        lv.hvals = L->hvals;
+        lv.first0 = L->first0;
+        lv.hmask = (uint32_t)(L->hcap - 1);
+        lv.ncells = L->ncells;
+        lv.s = sl;
+        lv.parent = nullptr;
         if ((top && nlev >= 2) || sl == 21 || nlev == kMaxLevels) break;
+        // level l + 1
+        Level* U = &g->lev[l + 1];
+        const uint32_t nc = L->ncells;
+        hipLaunchKernelGGL(up_flag_k, dim3(grid_for(nc)), dim3(kBlock), 0, c->stream, L->key, nc, flag);
+        PDD_HIP(c, hipGetLastError());
+        if ((rc = exclusive_scan_u32(c, flag, pos, nc, pos + nc))) return rc;
+        if ((rc = read_count(c, pos + nc, &U->ncells))) return rc;
+        if ((rc = alloc_dev(c, (void**)&L->parent, (size_t)nc * 4))) return rc;
+        if ((rc = alloc_dev(c, (void**)&U->start, (size_t)(U->ncells + 1) * 4))) return rc;
+        if ((rc = alloc_dev(c, (void**)&U->key, (size_t)U->ncells * 8))) return rc;
+        if ((rc = alloc_dev(c, (void**)&U->first0, (size_t)(U->ncells + 1) * 4))) return rc;
+        hipLaunchKernelGGL(up_write_k, dim3(grid_for(nc)), dim3(kBlock), 0, c->stream, L->key, L->start, L->first0, nc,
+                           n, l0->ncells, flag, pos, L->parent, U->start, U->key, U->first0, U->ncells);
+        PDD_HIP(c, hipGetLastError());
+        if ((rc = build_hash(c, U))) return rc;
+        lv.parent = L->parent;
+        v.lv[l + 1].base = total;
+        total += U->ncells;
+        nlev++;
     }
+    v.lv[0].base = 0;
     v.nlev = nlev;
+    v.total_cells = total;
     return PDD_OK;
 }
 

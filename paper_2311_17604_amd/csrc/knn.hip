@@ -1,6 +1,4 @@
 // Initial k-nearest-neighbour lists and costs of every point (Eq. 11).
-#include <stdlib.h>
-
 #include <algorithm>
 
 #include "search.h"
@@ -8,33 +6,6 @@
 namespace pdd {
 
 namespace {
-
-// One lane per query in Morton order, so the lanes of a wave share cells.
-template <int K>
-__global__ void __launch_bounds__(kBlock) knn_all_k(GridView g, int k, int32_t* __restrict__ nbr,
-                                                    uint8_t* __restrict__ cnt, uint64_t* __restrict__ cost,
-                                                    int64_t* __restrict__ r2k) {
-    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= g.n) return;
-    const int4 qp = g.pts[q];
-    TopK<K> t;
-    t.init();
-    SearchCtx sc{nullptr, nullptr, 0};
-    ring_search<K, kAll>(g, q, qp, sc, t, K);
-    const int c = t.count();
-    const int use = c < k ? c : k;
-#pragma unroll
-    for (int j = 0; j < K; j++) nbr[(size_t)q * K + j] = t.id[j];
-    cnt[q] = (uint8_t)c;
-    cost[q] = list_cost<K>(t, use);
-    if (r2k) {
-        uint64_t r = 0;
-#pragma unroll
-        for (int j = 0; j < K; j++)
-            if (j == use - 1) r = t.d[j];
-        r2k[q] = (int64_t)r;
-    }
-}
 
 // One wavefront per query (see wave_knn).
 template <int K>
@@ -51,7 +22,8 @@ __global__ void __launch_bounds__(kBlock) knn_wave_k(GridView g, int k, int32_t*
         SearchCtx sc{nullptr, nullptr, 0};
         uint64_t d;
         int32_t id;
-        wave_knn<K, kAll>(g, q, qp, sc, K, d, id, lds[w][0], lds[w][1]);
+        const int L0 = start_level(g, q, K + 1, nullptr);
+        wave_knn<K, kAll>(g, q, qp, sc, K, L0, d, id, lds[w][0], lds[w][1]);
         const int c = __popcll(__ballot(lane < K && d != ~0ull));
         const int use = c < k ? c : k;
         const uint64_t wsum = wave_sum64(lane < use ? cost_term(d) : 0ull);
@@ -85,26 +57,12 @@ __global__ void __launch_bounds__(kBlock) to_original_k(const int4* __restrict__
 
 int knn_all(Ctx* c, const GridView& g, int k, int K, KnnOut out, int64_t* fallbacks) {
     if (fallbacks) *fallbacks = 0;
-    dim3 grid((g.n + kBlock - 1) / kBlock), block(kBlock);
-    const char* mode = getenv("PDD_KNN_MODE");
-    if (!(mode && mode[0] == 'l')) {
-        const uint32_t nb = std::min<uint32_t>((g.n + 3) / 4, 16384u);
-        dim3 wg((nb + 7) / 8 * 8);
-        switch (K) {
-            case 8: hipLaunchKernelGGL(knn_wave_k<8>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
-            case 16: hipLaunchKernelGGL(knn_wave_k<16>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
-            case 24: hipLaunchKernelGGL(knn_wave_k<24>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
-            case 32: hipLaunchKernelGGL(knn_wave_k<32>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
-            default: return PDD_EINVAL;
-        }
-        PDD_HIP(c, hipGetLastError());
-        return PDD_OK;
-    }
+    const dim3 wg(std::min<uint32_t>((g.n + 3) / 4, 16384u)), block(kBlock);
     switch (K) {
-        case 8: hipLaunchKernelGGL(knn_all_k<8>, grid, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
-        case 16: hipLaunchKernelGGL(knn_all_k<16>, grid, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
-        case 24: hipLaunchKernelGGL(knn_all_k<24>, grid, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
-        case 32: hipLaunchKernelGGL(knn_all_k<32>, grid, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
+        case 8: hipLaunchKernelGGL(knn_wave_k<8>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
+        case 16: hipLaunchKernelGGL(knn_wave_k<16>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
+        case 24: hipLaunchKernelGGL(knn_wave_k<24>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
+        case 32: hipLaunchKernelGGL(knn_wave_k<32>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k); break;
         default: return PDD_EINVAL;
     }
     PDD_HIP(c, hipGetLastError());

@@ -23,13 +23,14 @@ struct RoundDev {
     int32_t top_orig, pad2;
     float frac;                   // share of alive points ranked this round (adapted)
     float frac_max;
+    uint32_t work;                // survivors enumerated by the danger checks, this round
+    uint32_t pad3;
     uint64_t surv_min[kLev];      // lowest survivor cost per key level, this round
 };
 
 struct RoundArrays {
     const int4* pts;
-    const uint32_t* cell_of;
-    const uint32_t* coarse_of;
+    const uint32_t* of0;    // [n] level-0 cell of each point
     uint8_t* alive;
     uint64_t* cost;
     int32_t* nbr;       // [n*K]
@@ -56,19 +57,20 @@ struct RoundArrays {
     int32_t* head;       // [n] pool chains
     int32_t* pool_src;
     int32_t* pool_next;
-    uint32_t* cell_alive;   // [ncells]
-    uint32_t* cellAlev;     // [ncells * kLev] A points per cell and level, this round
-    uint32_t* ccell_alive;  // [nccells]
-    uint32_t* ccellAlev;    // [nccells * kLev]
-    uint32_t* ccS;          // [nccells + 1] survivors per coarse cell, this round
-    uint32_t* surv_off;     // [nccells + 1] exclusive scan of ccS
+    uint32_t* cell_alive;   // [total cells] alive points per cell, all levels (index base + cell)
+    uint32_t* cellAlev;     // [total cells * kLev] A points per cell and key level, this round
     uint32_t* surv_list;    // [n] survivors of this round
-    uint32_t* surv_bucket;  // [n] survivors grouped by coarse cell
+    const uint32_t* grp_lo; // [n] run of points with identical coordinates around each
+    const uint32_t* grp_hi; //     point in Morton order: [grp_lo, grp_hi)
+    uint32_t* gsafe;        // [n] round stamp: at least k alive identical points rank below
+    uint32_t* cS;           // [ncells0 + 1] survivors per level-0 cell, this round
+    uint32_t* surv_off;     // [ncells0 + 1] exclusive scan of cS
+    uint32_t* surv_bucket;  // [n] survivors grouped by level-0 cell, in cell order
     RoundDev* st;
     int k, K;
     float frac;
     int check;
-    uint32_t nccells;
+    uint32_t ncells0;
 };
 
 __device__ inline uint32_t wave_append(uint32_t* counter, bool pred) {

@@ -78,6 +78,7 @@ __global__ void rb_begin(RoundArrays a) {
                 st->mode = 0;
                 st->top_cost = 0;
                 st->top_orig = 0x7FFFFFFF;
+                st->work = 0;
                 for (int j = 0; j < kLev; j++) st->surv_min[j] = ~0ull;
             }
         }
@@ -147,26 +148,31 @@ __global__ void __launch_bounds__(kBlock) rb_find0(RoundArrays a) {
     find_bin(a.hist, kSelBins0, st->m, &b, &need);
     if (threadIdx.x == 0) {
         st->sel_bin = b;
-        // A = every bin above b when that is not empty; else the exact top m
-        // out of bin b (all of the top m lie in it)
+        // A = the bins above b, plus (mode 1) the exact top `need` of bin b
+        // when the bins above hold less than half of m
         const uint32_t above = st->m - need;
-        st->mode = above >= 1 ? 0u : 1u;
-        st->sel_need = st->m;
+        const uint32_t mode = 2 * above >= st->m ? 0u : 1u;
+        st->mode = mode;
+        st->sel_need = need;
         const int e = (int)(b / 64u) - 1;
         st->sel_rem = (e >= 6 ? e - 6 : 0) + 31;
-        // key levels: split the bins above b into kLev parts of about equal count
+        // key levels: split A into kLev parts of about equal count by bin
+        // (the part taken from bin b is in level 0)
         st->lev_t[0] = 0;
         for (int j = 1; j < kLev; j++) st->lev_t[j] = 0xFFFFFFFFu;
         for (int j = 0; j < kLev; j++) st->glob_block[j] = 0;
-        if (above >= 1) {
-            uint32_t cum = 0;
-            int j = 1;
-            for (uint32_t bb = b + 1; bb < (uint32_t)kSelBins0 && j < kLev; bb++) {
-                cum += a.hist[bb];
-                while (j < kLev && (uint64_t)cum * kLev >= (uint64_t)above * j) {
-                    st->lev_t[j] = bb + 1;
-                    j++;
-                }
+        const uint64_t total = mode == 0 ? above : st->m;
+        uint64_t cum = mode == 0 ? 0 : need;
+        int j = 1;
+        while (j < kLev && cum * kLev >= total * j && total > cum) {
+            st->lev_t[j] = b + 1;
+            j++;
+        }
+        for (uint32_t bb = b + 1; bb < (uint32_t)kSelBins0 && j < kLev; bb++) {
+            cum += a.hist[bb];
+            while (j < kLev && cum * kLev >= total * j) {
+                st->lev_t[j] = bb + 1;
+                j++;
             }
         }
     }
@@ -180,7 +186,7 @@ __global__ void __launch_bounds__(kBlock) rb_collect0(RoundArrays a, int par) {
     constexpr int IPT = 8;
     for (uint32_t base = blockIdx.x * kBlock * IPT; base < na; base += gridDim.x * kBlock * IPT) {
         uint32_t item[IPT];
-        uint32_t sel = 0, nsel = 0;
+        uint32_t selA = 0, selC = 0, nA = 0, nC = 0;
 #pragma unroll
         for (int e = 0; e < IPT; e++) {
             const uint32_t t = base + e * kBlock + threadIdx.x;
@@ -188,24 +194,26 @@ __global__ void __launch_bounds__(kBlock) rb_collect0(RoundArrays a, int par) {
             if (t < na) {
                 const uint32_t i = L[t];
                 const uint32_t bb = bin0(a.cost[i]);
-                if (mode == 0 ? bb > bsel : bb == bsel) {
-                    item[e] = i;
-                    sel |= 1u << e;
-                    nsel++;
+                item[e] = i;
+                if (bb > bsel) {
+                    selA |= 1u << e;
+                    nA++;
+                } else if (mode == 1 && bb == bsel) {
+                    selC |= 1u << e;
+                    nC++;
                 }
             }
         }
-        uint32_t p = block_reserve(mode == 0 ? &st->nA : &st->nCand, nsel);
+        uint32_t pA = block_reserve(&st->nA, nA);
+        uint32_t pC = mode == 1 ? block_reserve(&st->nCand, nC) : 0u;
 #pragma unroll
         for (int e = 0; e < IPT; e++) {
-            if (!((sel >> e) & 1u)) continue;
-            if (mode == 0) {
-                a.A[p] = item[e];
+            if ((selA >> e) & 1u) {
+                a.A[pA++] = item[e];
                 a.inA[item[e]] = round;
-            } else {
-                a.cand[0][p] = item[e];
+            } else if ((selC >> e) & 1u) {
+                a.cand[0][pC++] = item[e];
             }
-            p++;
         }
     }
 }
@@ -307,7 +315,7 @@ __global__ void __launch_bounds__(1024) rb_refine(RoundArrays a) {
 // removal and re-costing
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(kBlock) rb_remove(RoundArrays a) {
+__global__ void __launch_bounds__(kBlock) rb_remove(RoundArrays a, GridView g) {
     RoundDev* st = a.st;
     if (st->done || st->err) return;
     const uint32_t nA = st->nA, round = st->round;
@@ -317,8 +325,10 @@ __global__ void __launch_bounds__(kBlock) rb_remove(RoundArrays a) {
         bool rm = false;
         if (t < nA) {
             x = a.A[t];
-            rm = a.blocked[x] != round;
-            if (rm) {
+            // an identical point ranked below is a witness for everything:
+            // with k of them x is removed whatever its neighbours do
+            rm = a.gsafe[x] == round;
+            if (!rm && a.blocked[x] != round) {
                 // a dangerous point with no bound for this level makes every
                 // survivor of the level at or below its cost wait (except the
                 // round's highest key, which no point can precede)
@@ -326,10 +336,13 @@ __global__ void __launch_bounds__(kBlock) rb_remove(RoundArrays a) {
                 const bool top = cx == st->top_cost && a.pts[x].w == st->top_orig;
                 rm = top || cx >= st->glob_block[level_of(st, cx)];
             }
+            // clear this round's A counts of x's cells at every level
+            uint32_t c = a.of0[x];
+            for (int L = 0; L < g.nlev; L++) {
+                const size_t gc = (size_t)(g.lv[L].base + c) * kLev;
 #pragma unroll
-            for (int j = 0; j < kLev; j++) {
-                a.cellAlev[(size_t)a.cell_of[x] * kLev + j] = 0;
-                a.ccellAlev[(size_t)a.coarse_of[x] * kLev + j] = 0;
+                for (int j = 0; j < kLev; j++) a.cellAlev[gc + j] = 0;
+                if (L + 1 < g.nlev) c = g.lv[L].parent[c];
             }
         }
         const uint32_t p = wave_append(&st->nR, rm);
@@ -338,8 +351,11 @@ __global__ void __launch_bounds__(kBlock) rb_remove(RoundArrays a) {
             a.ev_cost[st->removed + p] = a.cost[x];
             a.ev_orig[st->removed + p] = a.pts[x].w;
             a.alive[x] = 0;
-            atomicSub(&a.cell_alive[a.cell_of[x]], 1u);
-            atomicSub(&a.ccell_alive[a.coarse_of[x]], 1u);
+            uint32_t c = a.of0[x];
+            for (int L = 0; L < g.nlev; L++) {
+                atomicSub(&a.cell_alive[g.lv[L].base + c], 1u);
+                if (L + 1 < g.nlev) c = g.lv[L].parent[c];
+            }
         }
     }
 }
@@ -351,10 +367,12 @@ __global__ void rb_remove_end(RoundArrays a) {
     st->removed += st->nR;
     st->stat_surv += st->nSurv;
     // adapt the ranked share: a round that frees few of A (a dense region
-    // filling A) ranks fewer points next time; a productive one more
+    // filling A), or whose danger checks enumerate many survivors (their
+    // number grows faster than A), ranks fewer points next time; a
+    // productive and cheap one more
     const float yield = (float)st->nR / (float)(st->nA ? st->nA : 1);
-    if (yield < 0.05f) st->frac = fmaxf(st->frac * 0.5f, 1e-5f);
-    else if (yield > 0.2f) st->frac = fminf(st->frac * 1.5f, st->frac_max);
+    if (yield < 0.05f || st->work > (4u << 20)) st->frac = fmaxf(st->frac * 0.5f, 1e-5f);
+    else if (yield > 0.2f && st->work < (1u << 20)) st->frac = fminf(st->frac * 1.5f, st->frac_max);
 }
 
 __device__ inline void touch(const RoundArrays& a, RoundDev* st, uint32_t z, uint32_t round) {
@@ -429,7 +447,8 @@ __global__ void __launch_bounds__(kBlock) rb_research(RoundArrays a, GridView g)
         SearchCtx sc{a.alive, nullptr, 0};
         uint64_t d;
         int32_t id;
-        wave_knn<K, kAlive>(g, z, pz, sc, K, d, id, lds[w][0], lds[w][1]);
+        const int L0 = start_level(g, z, K + 1, a.cell_alive);
+        wave_knn<K, kAlive>(g, z, pz, sc, K, L0, d, id, lds[w][0], lds[w][1]);
         const int c = __popcll(__ballot(lane < K && d != ~0ull));
         const int use = c < k ? c : k;
         const uint64_t wsum = wave_sum64(lane < use ? cost_term(d) : 0ull);
@@ -523,8 +542,31 @@ __global__ void rd_init(RoundDev* st, uint32_t n, uint32_t target, uint32_t pool
     z.target = target;
     z.pool_cap = pool_cap;
     z.frac = frac;
-    z.frac_max = frac;
+    z.frac_max = fminf(4.0f * frac, 1.0f);
     *st = z;
+}
+
+// Runs of identical coordinates (equal Morton codes, hence adjacent in the
+// sorted order): the first point of a run writes the run to all its points.
+__global__ void __launch_bounds__(kBlock) grp_init_k(const int4* __restrict__ pts, uint32_t n,
+                                                     uint32_t* __restrict__ lo, uint32_t* __restrict__ hi) {
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+        const int4 p = pts[j];
+        if (j > 0) {
+            const int4 q = pts[j - 1];
+            if (q.x == p.x && q.y == p.y && q.z == p.z) continue;
+        }
+        uint32_t e = j + 1;
+        while (e < n) {
+            const int4 q = pts[e];
+            if (q.x != p.x || q.y != p.y || q.z != p.z) break;
+            e++;
+        }
+        for (uint32_t i = j; i < e; i++) {
+            lo[i] = j;
+            hi[i] = e;
+        }
+    }
 }
 
 __global__ void __launch_bounds__(kBlock) cell_count_k(const uint32_t* __restrict__ start, uint32_t ncells,
@@ -585,10 +627,11 @@ enum {
     kSAlive = 10, kSCost, kSNbr, kSCnt, kSInA, kSBlocked, kSTouched, kSAl0, kSAl1, kSA, kSC0, kSC1, kSDgY,
     kSTouch, kSResearch, kSR, kSEvC, kSEvO, kSHist, kSRevOff, kSRevSrc, kSHead, kSPoolS, kSPoolN, kSSt, kSTmp,
     kSFin1, kSFin2, kSSurv,
-    kSCellAlive = 60, kSCellA, kSCCellAlive, kSCCellA, kSCCS, kSDgC, kSDgO, kSDgD, kSSurvOff, kSSurvList,
-    kSSurvBucket
+    kSCellAlive = 60, kSCellA, kSDgC, kSDgO, kSDgD, kSSurvOff, kSSurvList, kSSurvBucket, kSCS, kSGrpLo, kSGrpHi,
+    kSGSafe
 };
 static_assert(kSSurv < 40, "scratch slots overlap the scan's");
+static_assert(kSGSafe < 96, "scratch slots beyond the context's table");
 
 int build_reverse(Ctx* c, RoundArrays& a, uint32_t n) {
     uint32_t* deg = (uint32_t*)scratch(c, kSTmp, (size_t)(n + 1) * 4);
@@ -618,7 +661,7 @@ int launch_round(Ctx* c, RoundArrays& a, const GridView& g, int par) {
     PDD_HIP(c, hipGetLastError());
     int rc = launch_blocking(c, a, g, K);
     if (rc) return rc;
-    hipLaunchKernelGGL(rb_remove, dim3(G), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(rb_remove, dim3(G), dim3(kBlock), 0, c->stream, a, g);
     hipLaunchKernelGGL(rb_remove_end, dim3(1), dim3(1), 0, c->stream, a);
     hipLaunchKernelGGL(rb_touch, dim3(G), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_recost, dim3(G), dim3(kBlock), 0, c->stream, a);
@@ -649,10 +692,10 @@ int run_rounds(Ctx* c, RoundArrays& a, const GridView& g, uint32_t n) {
             c->stats[7] = hst->stat_touch;
             return PDD_OK;
         }
-        if (c->progress && (hst->round % 50 == 0)) {
+        if (c->progress && hst->round % 50 == 0) {
             fprintf(stderr, "pdd: round %u removed %u/%u alive %u A %u removed-now %u danger %u survivors %u "
-                    "researched %u\n", hst->round, hst->removed, hst->target, hst->n_alive_new, hst->nA, hst->nR,
-                    hst->nDanger, hst->nSurv, hst->nResearch);
+                    "researched %u enumerated %u frac %g\n", hst->round, hst->removed, hst->target, hst->n_alive_new, hst->nA, hst->nR,
+                    hst->nDanger, hst->nSurv, hst->nResearch, hst->work, hst->frac);
             fflush(stderr);
         }
         // rebuild the reverse lists when the appended chains overflowed or
@@ -677,9 +720,8 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, int6
     const uint32_t target = (uint32_t)(n - keep);
     RoundArrays a{};
     a.pts = g.pts;
-    a.cell_of = g.lv[0].of;
-    a.coarse_of = g.lv[1].of;
-    const uint32_t ncells = g.lv[0].ncells, nccells = g.lv[1].ncells;
+    a.of0 = g.of0;
+    const uint32_t ncells0 = g.lv[0].ncells, tcells = g.total_cells;
     a.k = k;
     a.K = K;
     a.frac = frac;
@@ -718,15 +760,19 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, int6
     ALLOC(head, kSHead, (size_t)n * 4);
     ALLOC(pool_src, kSPoolS, pool_cap * 4);
     ALLOC(pool_next, kSPoolN, pool_cap * 4);
-    ALLOC(cell_alive, kSCellAlive, (size_t)ncells * 4);
-    ALLOC(cellAlev, kSCellA, (size_t)ncells * kLev * 4);
-    ALLOC(ccell_alive, kSCCellAlive, (size_t)nccells * 4);
-    ALLOC(ccellAlev, kSCCellA, (size_t)nccells * kLev * 4);
-    ALLOC(ccS, kSCCS, (size_t)(nccells + 1) * 4);
-    ALLOC(surv_off, kSSurvOff, (size_t)(nccells + 1) * 4);
+    ALLOC(cell_alive, kSCellAlive, (size_t)tcells * 4);
+    ALLOC(cellAlev, kSCellA, (size_t)tcells * kLev * 4);
+    ALLOC(surv_off, kSSurvOff, (size_t)(ncells0 + 1) * 4);
     ALLOC(surv_list, kSSurvList, (size_t)n * 4);
     ALLOC(surv_bucket, kSSurvBucket, (size_t)n * 4);
-    a.nccells = nccells;
+    ALLOC(cS, kSCS, (size_t)(ncells0 + 1) * 4);
+    uint32_t *glo, *ghi;
+    if (!(glo = (uint32_t*)scratch(c, kSGrpLo, (size_t)n * 4)) || !(ghi = (uint32_t*)scratch(c, kSGrpHi, (size_t)n * 4)))
+        return PDD_ENOMEM;
+    a.grp_lo = glo;
+    a.grp_hi = ghi;
+    ALLOC(gsafe, kSGSafe, (size_t)n * 4);
+    a.ncells0 = ncells0;
     ALLOC(st, kSSt, sizeof(RoundDev));
 #undef ALLOC
     int rc;
@@ -735,14 +781,14 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, int6
     if ((rc = fill_u32(c, a.blocked, 0, n))) return rc;
     if ((rc = fill_u32(c, a.touched, 0, n))) return rc;
     if ((rc = fill_u32(c, a.surv, 0, n))) return rc;
-    if ((rc = fill_u32(c, a.cellAlev, 0, (size_t)ncells * kLev))) return rc;
-    if ((rc = fill_u32(c, a.ccellAlev, 0, (size_t)nccells * kLev))) return rc;
-    if ((rc = fill_u32(c, a.ccS, 0, nccells + 1))) return rc;
+    if ((rc = fill_u32(c, a.cellAlev, 0, (size_t)tcells * kLev))) return rc;
+    if ((rc = fill_u32(c, a.cS, 0, ncells0 + 1))) return rc;
+    if ((rc = fill_u32(c, a.gsafe, 0, n))) return rc;
+    hipLaunchKernelGGL(grp_init_k, dim3(gfor(n)), dim3(kBlock), 0, c->stream, g.pts, n, glo, ghi);
     if ((rc = iota_u32(c, a.alive_list[0], n))) return rc;
-    hipLaunchKernelGGL(cell_count_k, dim3(gfor(ncells)), dim3(kBlock), 0, c->stream, g.lv[0].start, ncells,
-                       a.cell_alive);
-    hipLaunchKernelGGL(cell_count_k, dim3(gfor(nccells)), dim3(kBlock), 0, c->stream, g.lv[1].start, nccells,
-                       a.ccell_alive);
+    for (int L = 0; L < g.nlev; L++)
+        hipLaunchKernelGGL(cell_count_k, dim3(gfor(g.lv[L].ncells)), dim3(kBlock), 0, c->stream, g.lv[L].start,
+                           g.lv[L].ncells, a.cell_alive + g.lv[L].base);
     hipLaunchKernelGGL(rd_init, dim3(1), dim3(1), 0, c->stream, a.st, n, target, (uint32_t)pool_cap, frac);
     PDD_HIP(c, hipGetLastError());
 

@@ -11,48 +11,6 @@
 
 namespace pdd {
 
-// Top-K by squared distance, ascending, in registers.  A candidate at the
-// same distance as the current K-th is not inserted: among equal distances
-// the first one seen stays, which leaves the multiset of distances exact.
-template <int K>
-struct TopK {
-    uint64_t d[K];
-    int32_t id[K];
-
-    __device__ inline void init() {
-#pragma unroll
-        for (int j = 0; j < K; j++) {
-            d[j] = ~0ull;
-            id[j] = -1;
-        }
-    }
-
-    __device__ inline void push(uint64_t dd, int32_t ii) {
-        if (dd >= d[K - 1]) return;
-#pragma unroll
-        for (int j = K - 1; j > 0; --j) {
-            if (dd < d[j - 1]) {
-                d[j] = d[j - 1];
-                id[j] = id[j - 1];
-            } else if (dd < d[j]) {
-                d[j] = dd;
-                id[j] = ii;
-            }
-        }
-        if (dd < d[0]) {
-            d[0] = dd;
-            id[0] = ii;
-        }
-    }
-
-    __device__ inline int count() const {
-        int c = 0;
-#pragma unroll
-        for (int j = 0; j < K; j++) c += d[j] != ~0ull;
-        return c;
-    }
-};
-
 // Which points a search may return besides excluding the query itself.
 enum SearchMode { kAll = 0, kAlive = 1, kAliveNotA = 2 };
 
@@ -79,83 +37,40 @@ __device__ inline uint64_t face_gap2(int u, int cu, int r, int s, int cmax) {
     return g;
 }
 
-template <int K, int MODE>
-__device__ inline void scan_cell(const GridView& g, const LevelView& lv, uint32_t c, uint32_t q, int qx, int qy,
-                                 int qz, const SearchCtx& sc, TopK<K>& t) {
-    const uint32_t b = lv.start[c], e = lv.start[c + 1];
-    for (uint32_t j = b; j < e; j++) {
-        if (j == q) continue;
-        if (MODE != kAll) {
-            if (!sc.alive[j]) continue;
-            if (MODE == kAliveNotA && sc.inA[j] == sc.round) continue;
-        }
-        int4 p = g.pts[j];
-        t.push(dist2(qx, qy, qz, p.x, p.y, p.z), (int32_t)j);
-    }
-}
-
-template <int K, int MODE>
-__device__ inline void scan_cell_at(const GridView& g, const LevelView& lv, int x, int y, int z, uint32_t q, int qx,
-                                    int qy, int qz, const SearchCtx& sc, TopK<K>& t) {
-    uint32_t c = hash_find(lv.hkeys, lv.hvals, lv.hmask, morton3((uint32_t)x, (uint32_t)y, (uint32_t)z));
-    if (c != kNone) scan_cell<K, MODE>(g, lv, c, q, qx, qy, qz, sc, t);
-}
-
-// Grows shells of cells around the query at the finest level, at most two
-// shells per level before moving one level up (edge x8, search restarted),
-// until entry kcert-1 is certified (no unsearched point can be nearer) or
-// the block covers the grid.  Returns the level that ended the search.
-template <int K, int MODE>
-__device__ int ring_search(const GridView& g, uint32_t q, int4 qp, const SearchCtx& sc, TopK<K>& t, int kcert) {
-    const int ux = qp.x - g.minx, uy = qp.y - g.miny, uz = qp.z - g.minz;
-    for (int L = 0; L < g.nlev; L++) {
+// Level at which a search around sorted point j starts: one below the
+// finest level whose cell around j holds at least `need` points (alive
+// points when alive_cnt, indexed by level base + cell, is given), so that the
+// 3x3x3 block there usually holds the neighbourhood.
+__device__ inline int start_level(const GridView& g, uint32_t j, uint32_t need, const uint32_t* alive_cnt) {
+    uint32_t c = g.of0[j];
+    int L = 0;
+    for (;;) {
         const LevelView& lv = g.lv[L];
-        const int s = lv.s;
-        const int cx = ux >> s, cy = uy >> s, cz = uz >> s;
-        const int rmax = (L == g.nlev - 1) ? (1 << 22) : 2;
-        if (L > 0) t.init();
-        for (int r = 0; r <= rmax; r++) {
-            if (r == 0) {
-                scan_cell_at<K, MODE>(g, lv, cx, cy, cz, q, qp.x, qp.y, qp.z, sc, t);
-            } else {
-                const int z0 = max(cz - r, 0), z1 = min(cz + r, lv.cmax[2]);
-                const int y0 = max(cy - r, 0), y1 = min(cy + r, lv.cmax[1]);
-                const int x0 = max(cx - r, 0), x1 = min(cx + r, lv.cmax[0]);
-                for (int z = z0; z <= z1; z++) {
-                    const bool zface = (z == cz - r) || (z == cz + r);
-                    for (int y = y0; y <= y1; y++) {
-                        const bool yface = (y == cy - r) || (y == cy + r);
-                        if (zface || yface) {
-                            for (int x = x0; x <= x1; x++)
-                                scan_cell_at<K, MODE>(g, lv, x, y, z, q, qp.x, qp.y, qp.z, sc, t);
-                        } else {
-                            if (cx - r >= 0) scan_cell_at<K, MODE>(g, lv, cx - r, y, z, q, qp.x, qp.y, qp.z, sc, t);
-                            if (cx + r <= lv.cmax[0])
-                                scan_cell_at<K, MODE>(g, lv, cx + r, y, z, q, qp.x, qp.y, qp.z, sc, t);
-                        }
-                    }
-                }
-            }
-            uint64_t g2 = face_gap2(ux, cx, r, s, lv.cmax[0]);
-            uint64_t gy = face_gap2(uy, cy, r, s, lv.cmax[1]);
-            uint64_t gz = face_gap2(uz, cz, r, s, lv.cmax[2]);
-            if (gy < g2) g2 = gy;
-            if (gz < g2) g2 = gz;
-            if (g2 == ~0ull) return L;  // the block covers the grid
-            if (t.d[kcert - 1] != ~0ull && t.d[kcert - 1] <= g2) return L;
-        }
+        const uint32_t cnt = alive_cnt ? alive_cnt[lv.base + c] : lv.start[c + 1] - lv.start[c];
+        if (cnt >= need || L + 1 >= g.nlev) break;
+        c = lv.parent[c];
+        L++;
     }
-    return g.nlev;  // not reached: the top level's block grows until it covers the grid
+    return L > 0 ? L - 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
-// One wavefront per query.  The 64 lanes look up the cells of a shell at
-// once, pack the points of the found cells into chunks of 64 (a wave prefix
-// sum over the cell sizes, then a binary search per lane), and test one
-// point each.  The top-K list is spread over the lanes (lane j holds the
-// j-th nearest); a candidate below the K-th distance is inserted with one
-// ballot (its rank) and one lane shift.  Same levels, shells and
-// certification as ring_search, same tie rule as TopK.
+// One wavefront per query.  The search starts at level L0 and grows the
+// block of cells around the query one shell at a time: shells 0 and 1 at
+// each level, then one level up (edge x2), whose 3x3x3 block contains the
+// previous one; points of the previous block are skipped there, so every
+// point is tested once.  It stops once entry kcert-1 is certified (every
+// point not yet tested lies at least that far) or the block covers the grid;
+// at the top level the shells keep growing.
+//
+// Per shell, the 64 lanes look up its cells at once, pack the points of the
+// found cells into chunks of 64 (a wave prefix sum over the cell sizes, then
+// a binary search per lane) and test one point each.  The list is spread
+// over the lanes (lane j holds the j-th nearest); a candidate below the K-th
+// distance is inserted with one ballot (its rank) and one lane shift.  A
+// candidate at the same distance as the current K-th is not inserted: among
+// equal distances the first one seen stays, which leaves the multiset of
+// distances exact.
 // ---------------------------------------------------------------------------
 
 __device__ inline uint64_t readlane64(uint64_t v, int l) {
@@ -179,21 +94,21 @@ __device__ inline void wave_sync_lds() {
 // lds_start / lds_excl: 64 entries of wave-private LDS each.  On return lane
 // j < K holds the j-th nearest (my_d = ~0 past the end).
 template <int K, int MODE>
-__device__ void wave_knn(const GridView& g, uint32_t q, int4 qp, const SearchCtx& sc, int kcert, uint64_t& my_d,
-                         int32_t& my_id, uint32_t* lds_start, uint32_t* lds_excl) {
+__device__ void wave_knn(const GridView& g, uint32_t q, int4 qp, const SearchCtx& sc, int kcert, int L0,
+                         uint64_t& my_d, int32_t& my_id, uint32_t* lds_start, uint32_t* lds_excl) {
     const int lane = (int)lane_id();
     const int ux = qp.x - g.minx, uy = qp.y - g.miny, uz = qp.z - g.minz;
     my_d = ~0ull;
     my_id = -1;
-    for (int L = 0; L < g.nlev; L++) {
+    uint64_t cert = 0;  // squared radius around the query within which every point was tested
+    for (int L = L0; L < g.nlev; L++) {
         const LevelView& lv = g.lv[L];
         const int s = lv.s;
         const int cx = ux >> s, cy = uy >> s, cz = uz >> s;
-        const int rmax = (L == g.nlev - 1) ? (1 << 22) : 2;
-        if (L > 0) {
-            my_d = ~0ull;
-            my_id = -1;
-        }
+        const int rmax = (L == g.nlev - 1) ? (1 << 22) : 1;
+        // the previous level's block, already tested
+        const bool skip = L > L0;
+        const int ps = s - 1, px = ux >> ps, py = uy >> ps, pz = uz >> ps;
         for (int r = 0; r <= rmax; r++) {
             const int side = 2 * r + 1;
             const int ncube = side * side * side;
@@ -244,7 +159,11 @@ __device__ void wave_knn(const GridView& g, uint32_t q, int4 qp, const SearchCtx
                         }
                         if (ok) {
                             const int4 p = g.pts[j];
-                            d = dist2(qp.x, qp.y, qp.z, p.x, p.y, p.z);
+                            if (skip && abs(((p.x - g.minx) >> ps) - px) <= 1 && abs(((p.y - g.miny) >> ps) - py) <= 1 &&
+                                abs(((p.z - g.minz) >> ps) - pz) <= 1)
+                                ok = false;
+                            else
+                                d = dist2(qp.x, qp.y, qp.z, p.x, p.y, p.z);
                         }
                     }
                     uint64_t thr = readlane64(my_d, K - 1);
@@ -278,8 +197,9 @@ __device__ void wave_knn(const GridView& g, uint32_t q, int4 qp, const SearchCtx
             if (gy < g2) g2 = gy;
             if (gz < g2) g2 = gz;
             if (g2 == ~0ull) return;
+            if (g2 > cert) cert = g2;
             const uint64_t kth = readlane64(my_d, kcert - 1);
-            if (kth != ~0ull && kth <= g2) return;
+            if (kth != ~0ull && kth <= cert) return;
         }
     }
 }
@@ -293,16 +213,6 @@ __device__ inline uint64_t wave_sum64(uint64_t v) {
         v += ((uint64_t)hi << 32) | lo;
     }
     return v;
-}
-
-// Cost of a sorted neighbour list: sum of cost_term over its first `use` entries.
-template <int K>
-__device__ inline uint64_t list_cost(const TopK<K>& t, int use) {
-    uint64_t w = 0;
-#pragma unroll
-    for (int j = 0; j < K; j++)
-        if (j < use) w += cost_term(t.d[j]);
-    return w;
 }
 
 }  // namespace pdd

@@ -126,6 +126,29 @@ def test_decimate_scan(gpu, oracle_mod, scale, frac):
         assert np.array_equal(g, r), name
 
 
+def _dup_cloud(seed, n_base, box, sizes):
+    """Random cloud plus groups of identical points (copies of random base
+    points), shuffled so that each group's members interleave in index order."""
+    rng = np.random.default_rng(seed)
+    P = scangen.random_cloud(n_base, box, seed)
+    groups = [np.repeat(P[rng.integers(0, n_base)][None, :], m, axis=0) for m in sizes]
+    Q = np.concatenate([P] + groups)
+    return np.ascontiguousarray(Q[rng.permutation(len(Q))])
+
+
+@pytest.mark.parametrize("seed,k,keep_frac,frac", [(1, 8, 0.25, 0.01), (2, 16, 0.1, 0.01), (3, 8, 0.5, 0.3),
+                                                   (4, 16, 0.2, 1.0), (5, 4, 0.05, 0.05)])
+def test_decimate_identical_groups(gpu, oracle_mod, seed, k, keep_frac, frac):
+    # large groups of identical points: all members share one cost, and a
+    # member with k identical points ranked below it goes in the same round
+    P = _dup_cloud(seed, 3000, 3000, [400, 250, 100, 40, 17, 16, 9, 5, 3, 2, 2])
+    keep = max(1, int(len(P) * keep_frac))
+    ref = oracle_mod.decimate(P, k, keep, b=8)
+    got = gpu_decimate(gpu, P, keep, k, round_frac=frac, check=True)
+    for g, r, name in zip(got, ref, ("kept", "order", "order_cost")):
+        assert np.array_equal(g, r), name
+
+
 def test_decimate_edges(gpu, oracle_mod):
     # keep everything, keep one, two points, all coincident, a line, 16-byte stride
     P = scangen.random_cloud(64, 50, 9)
