@@ -19,7 +19,7 @@ __global__ void __launch_bounds__(kBlock) knn_wave_k(GridView g, int k, int32_t*
     const uint32_t nw = gridDim.x * (kBlock / kWave);
     for (uint32_t q = blockIdx.x * (kBlock / kWave) + w; q < g.n; q += nw) {
         const int4 qp = g.pts[q];
-        SearchCtx sc{nullptr, nullptr, 0};
+        SearchCtx sc{nullptr};
         uint64_t d;
         int32_t id;
         const int L0 = start_level(g, q, K + 1, nullptr);

@@ -444,7 +444,7 @@ __global__ void __launch_bounds__(kBlock) rb_research(RoundArrays a, GridView g)
     for (uint32_t t = blockIdx.x * (kBlock / kWave) + w; t < nr; t += nw) {
         const uint32_t z = a.research_list[t];
         const int4 pz = a.pts[z];
-        SearchCtx sc{a.alive, nullptr, 0};
+        SearchCtx sc{a.alive};
         uint64_t d;
         int32_t id;
         const int L0 = start_level(g, z, K + 1, a.cell_alive);
@@ -546,6 +546,31 @@ __global__ void rd_init(RoundDev* st, uint32_t n, uint32_t target, uint32_t pool
     *st = z;
 }
 
+// Search view over the alive points: a compacted copy of the sorted points
+// that are alive (Morton order kept, sorted position in .w) and, for every
+// cell of every level, its range in that copy.  Re-searches scan it instead
+// of the full point array, whose cells fill up with removed points.
+__global__ void __launch_bounds__(kBlock) av_flag_k(const uint8_t* __restrict__ alive, uint32_t n,
+                                                    uint32_t* __restrict__ flag) {
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) flag[j] = alive[j];
+}
+
+__global__ void __launch_bounds__(kBlock) av_pack_k(const int4* __restrict__ pts, const uint8_t* __restrict__ alive,
+                                                    const uint32_t* __restrict__ pos, uint32_t n,
+                                                    int4* __restrict__ apts) {
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+        if (alive[j]) {
+            const int4 p = pts[j];
+            apts[pos[j]] = make_int4(p.x, p.y, p.z, (int)j);
+        }
+}
+
+__global__ void __launch_bounds__(kBlock) av_start_k(const uint32_t* __restrict__ start, uint32_t nc,
+                                                     const uint32_t* __restrict__ pos, uint32_t* __restrict__ astart) {
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c <= nc; c += gridDim.x * blockDim.x)
+        astart[c] = pos[start[c]];
+}
+
 // Runs of identical coordinates (equal Morton codes, hence adjacent in the
 // sorted order): the first point of a run writes the run to all its points.
 __global__ void __launch_bounds__(kBlock) grp_init_k(const int4* __restrict__ pts, uint32_t n,
@@ -628,10 +653,10 @@ enum {
     kSTouch, kSResearch, kSR, kSEvC, kSEvO, kSHist, kSRevOff, kSRevSrc, kSHead, kSPoolS, kSPoolN, kSSt, kSTmp,
     kSFin1, kSFin2, kSSurv,
     kSCellAlive = 60, kSCellA, kSDgC, kSDgO, kSDgD, kSSurvOff, kSSurvList, kSSurvBucket, kSCS, kSGrpLo, kSGrpHi,
-    kSGSafe
+    kSGSafe, kSAPts, kSAStart, kSAFlag, kSAPos
 };
 static_assert(kSSurv < 40, "scratch slots overlap the scan's");
-static_assert(kSGSafe < 96, "scratch slots beyond the context's table");
+static_assert(kSAPos < 96, "scratch slots beyond the context's table");
 
 int build_reverse(Ctx* c, RoundArrays& a, uint32_t n) {
     uint32_t* deg = (uint32_t*)scratch(c, kSTmp, (size_t)(n + 1) * 4);
@@ -650,8 +675,34 @@ int build_reverse(Ctx* c, RoundArrays& a, uint32_t n) {
     return PDD_OK;
 }
 
+// (Re)builds the alive search view gs of grid g.
+int build_alive_view(Ctx* c, const RoundArrays& a, const GridView& g, GridView* gs) {
+    const uint32_t n = g.n;
+    int4* apts = (int4*)scratch(c, kSAPts, (size_t)n * sizeof(int4));
+    uint32_t* astart = (uint32_t*)scratch(c, kSAStart, ((size_t)g.total_cells + g.nlev) * 4);
+    uint32_t* flag = (uint32_t*)scratch(c, kSAFlag, (size_t)n * 4);
+    uint32_t* pos = (uint32_t*)scratch(c, kSAPos, (size_t)(n + 1) * 4);
+    if (!apts || !astart || !flag || !pos) return PDD_ENOMEM;
+    hipLaunchKernelGGL(av_flag_k, dim3(gfor(n)), dim3(kBlock), 0, c->stream, a.alive, n, flag);
+    PDD_HIP(c, hipGetLastError());
+    int rc = exclusive_scan_u32(c, flag, pos, n, pos + n);
+    if (rc) return rc;
+    hipLaunchKernelGGL(av_pack_k, dim3(gfor(n)), dim3(kBlock), 0, c->stream, g.pts, a.alive, pos, n, apts);
+    *gs = g;
+    gs->pts = apts;
+    size_t off = 0;
+    for (int L = 0; L < g.nlev; L++) {
+        hipLaunchKernelGGL(av_start_k, dim3(gfor(g.lv[L].ncells + 1)), dim3(kBlock), 0, c->stream, g.lv[L].start,
+                           g.lv[L].ncells, pos, astart + off);
+        gs->lv[L].start = astart + off;
+        off += g.lv[L].ncells + 1;
+    }
+    PDD_HIP(c, hipGetLastError());
+    return PDD_OK;
+}
+
 template <int K>
-int launch_round(Ctx* c, RoundArrays& a, const GridView& g, int par) {
+int launch_round(Ctx* c, RoundArrays& a, const GridView& g, const GridView& gs, int par) {
     const unsigned G = 1024;
     hipLaunchKernelGGL(rb_begin, dim3(1), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_hist0, dim3(G), dim3(kBlock), 0, c->stream, a, par);
@@ -665,7 +716,7 @@ int launch_round(Ctx* c, RoundArrays& a, const GridView& g, int par) {
     hipLaunchKernelGGL(rb_remove_end, dim3(1), dim3(1), 0, c->stream, a);
     hipLaunchKernelGGL(rb_touch, dim3(G), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_recost, dim3(G), dim3(kBlock), 0, c->stream, a);
-    hipLaunchKernelGGL(rb_research<K>, dim3(G), dim3(kBlock), 0, c->stream, a, g);
+    hipLaunchKernelGGL(rb_research<K>, dim3(G), dim3(kBlock), 0, c->stream, a, gs);
     hipLaunchKernelGGL(rb_compact, dim3(G), dim3(kBlock), 0, c->stream, a, par);
     PDD_HIP(c, hipGetLastError());
     return PDD_OK;
@@ -675,8 +726,12 @@ template <int K>
 int run_rounds(Ctx* c, RoundArrays& a, const GridView& g, uint32_t n) {
     RoundDev* hst = (RoundDev*)c->pinned;
     int par = 0;
+    GridView gs;
+    int rc = build_alive_view(c, a, g, &gs);
+    if (rc) return rc;
+    uint32_t view_alive = n;
     for (uint64_t it = 0;; it++) {
-        int rc = launch_round<K>(c, a, g, par);
+        rc = launch_round<K>(c, a, g, gs, par);
         if (rc) return rc;
         par ^= 1;
         PDD_HIP(c, hipMemcpyAsync(hst, a.st, sizeof(RoundDev), hipMemcpyDeviceToHost, c->stream));
@@ -699,10 +754,15 @@ int run_rounds(Ctx* c, RoundArrays& a, const GridView& g, uint32_t n) {
             fflush(stderr);
         }
         // rebuild the reverse lists when the appended chains overflowed or
-        // grew longer than one node per alive point on average
-        if (hst->overflow || hst->pool_count > hst->n_alive_new) {
+        // grew longer than three nodes per alive point on average
+        if (hst->overflow || hst->pool_count > 3 * hst->n_alive_new) {
             if ((rc = build_reverse(c, a, n))) return rc;
             c->stats[3]++;
+        }
+        // re-pack the alive search view once a third of its points are gone
+        if ((uint64_t)hst->n_alive_new * 3 < (uint64_t)view_alive * 2) {
+            if ((rc = build_alive_view(c, a, g, &gs))) return rc;
+            view_alive = hst->n_alive_new;
         }
         if (it > (uint64_t)n + 16) {
             c->err = "round loop made no progress";

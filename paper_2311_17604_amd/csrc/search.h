@@ -12,12 +12,15 @@
 namespace pdd {
 
 // Which points a search may return besides excluding the query itself.
-enum SearchMode { kAll = 0, kAlive = 1, kAliveNotA = 2 };
+//   kAll    every point; the grid's points are the sorted points and a
+//           point's id is its position
+//   kAlive  alive points; the grid view holds a compacted copy of the points
+//           that were alive when it was built (same cells, same Morton
+//           order), each with its sorted position in .w
+enum SearchMode { kAll = 0, kAlive = 1 };
 
 struct SearchCtx {
-    const uint8_t* alive;   // [n] 1 = alive (modes kAlive, kAliveNotA)
-    const uint32_t* inA;    // [n] round stamp of the current threshold set (kAliveNotA)
-    uint32_t round;
+    const uint8_t* alive;   // [n] 1 = alive (mode kAlive)
 };
 
 // Squared distance from relative coordinate u (cell cu) to the nearest point
@@ -151,20 +154,15 @@ __device__ void wave_knn(const GridView& g, uint32_t q, int4 qp, const SearchCtx
 #pragma unroll
                         for (int step = 32; step > 0; step >>= 1)
                             if (lds_excl[l + step] <= t) l += step;
-                        j = lds_start[l] + (t - lds_excl[l]);
+                        const uint32_t pos = lds_start[l] + (t - lds_excl[l]);
+                        const int4 p = g.pts[pos];
+                        j = MODE == kAll ? pos : (uint32_t)p.w;
                         bool ok = j != q;
-                        if (MODE != kAll && ok) {
-                            ok = sc.alive[j] != 0;
-                            if (MODE == kAliveNotA && ok) ok = sc.inA[j] != sc.round;
-                        }
-                        if (ok) {
-                            const int4 p = g.pts[j];
-                            if (skip && abs(((p.x - g.minx) >> ps) - px) <= 1 && abs(((p.y - g.miny) >> ps) - py) <= 1 &&
-                                abs(((p.z - g.minz) >> ps) - pz) <= 1)
-                                ok = false;
-                            else
-                                d = dist2(qp.x, qp.y, qp.z, p.x, p.y, p.z);
-                        }
+                        if (MODE != kAll && ok) ok = sc.alive[j] != 0;
+                        if (ok && skip && abs(((p.x - g.minx) >> ps) - px) <= 1 &&
+                            abs(((p.y - g.miny) >> ps) - py) <= 1 && abs(((p.z - g.minz) >> ps) - pz) <= 1)
+                            ok = false;
+                        if (ok) d = dist2(qp.x, qp.y, qp.z, p.x, p.y, p.z);
                     }
                     uint64_t thr = readlane64(my_d, K - 1);
                     uint64_t m = __ballot(d < thr);
