@@ -22,7 +22,7 @@ from paper_2311_17604_amd import scangen  # noqa: E402
 
 OUT = os.path.join(HERE, "oracle_hashes.json")
 
-# name -> (config index, scale)
+# name -> (workload index, scale); tests/test_gpu_golden.py repeats this table
 WORKLOADS = {
     "scan-200k-k8-keep25": (1, 1.0),
     "scan-20M-k16-keep10@0.25": (2, 0.25),
