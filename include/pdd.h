@@ -3,14 +3,14 @@
  * one AMD Instinct MI355X (gfx950).
  *
  * The method (arXiv 2311.17604):
- *   - cost of a point p (Eq. 11, Sec. 4.2): the sum of 1 / d(p, p')^2 over
+ *   - cost of a point p (Eq. 12, Sec. 4.2): the sum of 1 / d(p, p')^2 over
  *     its k nearest remaining neighbours p';
  *   - greedy removal (Sec. 4, Sec. 4.2): remove the remaining point of highest
  *     cost, update the costs its removal changes, repeat until exactly the
  *     requested number of points is left (Sec. 3: |C'| = lambda |C| with
  *     lambda = m / |C|).
  *
- * Exact integer reading used throughout (the paper's Eq. 11 is real-valued
+ * Exact integer reading used throughout (the paper's Eq. 12 is real-valued
  * and silent on ties and coincident points):
  *   d2(i, j) = sum over axes of (P_i - P_j)^2, int64, P in int32 millimetres;
  *   term(D)  = floor(2^56 / D) for D >= 1, 2^58 for D = 0;
@@ -102,7 +102,7 @@ int pdd_grid_info(const pdd_grid *grid, int64_t *ncells, int32_t *voxel_log2);
 
 /*
  * k-nearest-neighbour cost of every point of a grid over all its points
- * (Eq. 11 in the exact reading above).  Row i of each output belongs to the
+ * (Eq. 12 in the exact reading above).  Row i of each output belongs to the
  * input point i (original order).
  *   k, b    : 1 <= k, k + b <= 32
  *   d_nbr   : [n * (k+b)] int32 or NULL: original indices of the k+b nearest,

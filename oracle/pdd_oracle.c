@@ -9,11 +9,11 @@
  *   - d2(i, j)  = sum over axes of (P_i - P_j)^2 in int64, P in int32 mm.
  *   - term(D)   = floor(2^56 / D) for D >= 1, and 2^58 for D = 0.  This is
  *                 the fixed-point reading of the inverse squared distance of
- *                 Eq. 10/11 (Sec. 4.2); coincident points (D = 0, for which
+ *                 Eq. 11/12 (Sec. 4.2); coincident points (D = 0, for which
  *                 the real-valued cost is infinite) get a term above every
  *                 finite one.
  *   - W(i; S)   = sum of term(D) over the min(k, |S| - 1) smallest values of
- *                 the multiset { d2(i, j) : j in S, j != i }  (Eq. 11: the
+ *                 the multiset { d2(i, j) : j in S, j != i }  (Eq. 12: the
  *                 cost is a sum over the k-neighbourhood).
  *   - key(i)    = (W descending, original index ascending).
  *   - greedy    : repeatedly remove the alive point of highest key, emit

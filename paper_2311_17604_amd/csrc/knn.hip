@@ -1,4 +1,4 @@
-// Initial k-nearest-neighbour lists and costs of every point (Eq. 11).
+// Initial k-nearest-neighbour lists and costs of every point (Eq. 12).
 #include <algorithm>
 
 #include "search.h"

@@ -3,13 +3,13 @@
 * k-NN lists: O(n^2) brute force with an explicit (d2, index) sort, and
   scipy's cKDTree (a library routine) on the d2 multisets.
 * The fixed-point cost: the floor definition and its error against the
-  exact rational value of Eq. 11 (Sec. 4.2), computed with Fractions.
+  exact rational value of Eq. 12 (Sec. 4.2), computed with Fractions.
 * The greedy: a brute-force greedy that recomputes every cost from scratch
   before each removal (Sec. 4: remove the highest-cost sample, costs of the
   rest updated), on tiny inputs full of duplicates and ties.
 * Hand-derived cases: 1 mm line, alternating pair spacing, a duplicate
   pair, the two-close-points case of Fig. 3, k = 1 ranking = ascending
-  nearest-neighbour distance (Eq. 10).
+  nearest-neighbour distance (Eq. 11).
 * Invariants (Sec. 5, step 2 and Sec. 3): costs never rise, removal keys
   strictly decrease, exactly keep points remain, results independent of b.
 """
@@ -97,7 +97,7 @@ def test_knn_matches_ckdtree_on_scan(oracle_mod):
 
 
 # --------------------------------------------------------------------------
-# the cost term and Eq. 11
+# the cost term and Eq. 12
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("d2", [1, 2, 3, 5, 7, 1000, 999_983, 2**20 + 1, 3 * 2**42 - 1, 2**44 + 12345])
@@ -115,7 +115,7 @@ def test_term_zero_distance_ranks_above_every_finite_term(oracle_mod):
 
 @pytest.mark.parametrize("k,seed,box", [(1, 11, 300), (3, 12, 300), (6, 13, 60), (8, 14, 5000)])
 def test_cost_is_fixed_point_of_eq11(oracle_mod, k, seed, box):
-    """W = sum over the k nearest of 1/d^2 (Eq. 11), scaled by 2^56, each
+    """W = sum over the k nearest of 1/d^2 (Eq. 12), scaled by 2^56, each
     term floored: 0 <= 2^56 W_exact - W < k for clouds without duplicates."""
     P = scangen.random_cloud(200, box, seed)
     P = np.unique(P, axis=0)
@@ -131,7 +131,7 @@ def test_cost_is_fixed_point_of_eq11(oracle_mod, k, seed, box):
 
 
 def test_k1_ranking_is_ascending_nearest_distance(oracle_mod):
-    """Eq. 10: with k = 1 the cost is 1/d_p^2, so ranking by cost (desc,
+    """Eq. 11: with k = 1 the cost is 1/d_p^2, so ranking by cost (desc,
     then index) is ranking by nearest distance (asc, then index)."""
     P = scangen.config(1, scale=0.05).xyz
     _, r2k, cost = oracle_mod.knn_cost(P, 1, 0)
@@ -220,7 +220,7 @@ def test_fig3_two_close_points(oracle_mod):
     assert list(o1) == [3]
     _, o4, c4 = oracle_mod.decimate(P, 4, 4, b=0, check=True)
     assert list(o4) == [4]
-    # exact rational Eq. 11 agrees on which of the two is denser
+    # exact rational Eq. 12 agrees on which of the two is denser
     Q = P.tolist()
 
     def w(i):
