@@ -133,10 +133,14 @@ int pdd_knn_cost(pdd_ctx *ctx, const pdd_grid *grid, int32_t k, int32_t b, int32
 int pdd_decimate(pdd_ctx *ctx, const int32_t *d_xyz, int64_t n, int64_t keep_count,
                  const pdd_opts *opts, int32_t *d_kept, int32_t *d_order, uint64_t *d_order_cost);
 
-/* Counters of the last pdd_decimate on this context, written to stats[0..n):
- *   0 rounds, 1 re-searches (buffer exhausted), 2 rho searches, 3 reverse-list
- *   rebuilds, 4 fallback searches in the initial k-NN, 5 voxel_log2 used,
- *   6 k+b used, 7 touched (re-costed) points.
+/* Counters of the last pdd_decimate on this context, written to stats[0..n),
+ * n <= 12:
+ *   0 rounds, 1 re-searches (buffer exhausted), 2 danger checks, 3 reverse-list
+ *   rebuilds, 4 (unused, 0), 5 finest cell level (log2 mm), 6 list width used,
+ *   7 touched (re-costed) points, 8 points tested by the initial k-NN search,
+ *   9 predicted balls that certified a list, 10 predicted balls that did not
+ *   (those points fell back to the shell search), 11 (unused, 0).
+ * Entries 8-10 are also written by pdd_knn_cost.
  * Returns the number of counters written. */
 int pdd_last_stats(const pdd_ctx *ctx, int64_t *stats, int n);
 
@@ -146,6 +150,69 @@ int pdd_last_stats(const pdd_ctx *ctx, int64_t *stats, int n);
  * lists, 3 removal rounds, 4 finalisation (kept set and removal order).
  * Returns the number written. */
 int pdd_last_timing(const pdd_ctx *ctx, float *ms, int n);
+
+/*
+ * Learned search-radius bound (not part of the paper; it bounds the k-NN
+ * search of Sec. 5, which the paper does over the 26 voxels around a point's
+ * own voxel).  Per anchor cell, the finest grid cell around a point holding
+ * list-width + 1 points, a network predicts log2(r / cell edge), r an upper
+ * bound on the list-width-th neighbour distance of the cell's points, from
+ * 64 features: log1p of the point counts of the 4x4x4 cells of half the
+ * edge centred on the cell.  The search then tests only the cells meeting
+ * the ball of radius 2^margin * r and keeps the list when its last distance
+ * lies inside the ball; otherwise it falls back to the shell search.  So the
+ * predictor changes which points are tested, never a result.
+ *
+ * A network is trained for one list width (list(k + b) below) and bounds
+ * the searches of that width.
+ *
+ * Network: 64 -> 64 -> 64 -> 1 with ReLU; PDD_PRED_NPARAM parameters in
+ * fp32, flat: W1 [64 in][64 out], b1 [64], W2 [64][64], b2 [64], w3 [64],
+ * b3.  The products run in bf16 on matrix cores with fp32 accumulation.
+ * Loss: mean pinball loss at level tau, tau max(y - yhat, 0) +
+ * (1 - tau) max(yhat - y, 0); Adam (0.9, 0.999, 1e-8, bias-corrected).
+ * The parameters live in the context; the calls below are stream-ordered
+ * and synchronise before returning.
+ */
+#define PDD_PRED_NPARAM 8385
+
+/* Set (host array of n == PDD_PRED_NPARAM floats) or read back the
+ * parameters; setting also clears the Adam state.  Errors: PDD_EINVAL
+ * (wrong n, or reading before any set), PDD_ENOMEM, PDD_EHIP. */
+int pdd_pred_set_weights(pdd_ctx *ctx, const float *params, int64_t n);
+int pdd_pred_get_weights(pdd_ctx *ctx, float *params, int64_t n);
+
+/* Use (on != 0) or not the predicted radius in the initial k-NN of
+ * pdd_knn_cost and pdd_decimate; margin_log2 in [0, 8] is added to the
+ * predicted log2 radius.  Errors: PDD_EINVAL (no parameters set). */
+int pdd_pred_enable(pdd_ctx *ctx, int32_t on, float margin_log2);
+
+/* Training rows from a grid: runs the plain k-NN with list width
+ * list(k + b), then for every anchor cell (level >= 1) writes its 64 bf16
+ * features (d_feat [cap][64], uint16 bit patterns) and target
+ * log2(sqrt(max d2 of its points' last list entry)) - log2(cell edge)
+ * (d_target [cap] float; -8 when that distance is 0).  *count receives the
+ * number of anchor cells; rows beyond cap are not written.
+ * Errors: PDD_EINVAL, PDD_ENOMEM, PDD_EHIP. */
+int pdd_pred_samples(pdd_ctx *ctx, const pdd_grid *grid, int32_t k, int32_t b, uint16_t *d_feat,
+                     float *d_target, int64_t cap, int64_t *count);
+
+/* Network outputs of n feature rows (d_feat [n][64] bf16) into d_out [n].
+ * Errors: PDD_EINVAL (no parameters), PDD_EHIP. */
+int pdd_pred_forward(pdd_ctx *ctx, const uint16_t *d_feat, int64_t n, float *d_out);
+
+/* Gradient of the mean pinball loss over rows 0..n-1, 1 <= n <= 128, into
+ * d_grad [PDD_PRED_NPARAM]; the loss into d_loss [1] if not NULL.  No
+ * update.  Errors: PDD_EINVAL, PDD_EHIP. */
+int pdd_pred_grad(pdd_ctx *ctx, const uint16_t *d_feat, const float *d_target, int64_t n, float tau,
+                  float *d_grad, float *d_loss);
+
+/* `steps` Adam steps (learning rate lr) on minibatches of `batch` rows
+ * (16..128, a multiple of 16) drawn with replacement from the n rows by a
+ * counter-based hash of seed, step and row; the loss of each step into
+ * d_loss [steps] if not NULL.  Errors: PDD_EINVAL, PDD_ENOMEM, PDD_EHIP. */
+int pdd_pred_train(pdd_ctx *ctx, const uint16_t *d_feat, const float *d_target, int64_t n, int32_t steps,
+                   int32_t batch, float lr, float tau, uint64_t seed, float *d_loss);
 
 /* Static description of a status code. */
 const char *pdd_strerror(int status);

@@ -2,7 +2,7 @@
 #include <new>
 #include <string>
 
-#include "common.h"
+#include "predictor.h"
 
 namespace pdd {
 
@@ -102,6 +102,9 @@ void pdd_ctx_destroy(pdd_ctx* ctx) {
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->pred_P) (void)hipFree(c->pred_P);
+    if (c->pred_M) (void)hipFree(c->pred_M);
+    if (c->pred_V) (void)hipFree(c->pred_V);
     delete ctx;
 }
 
@@ -178,6 +181,7 @@ int pdd_decimate(pdd_ctx* ctx, const int32_t* d_xyz, int64_t n, int64_t keep_cou
     if (hipSetDevice(c->device) != hipSuccess) return PDD_EHIP;
     for (auto& s : c->stats) s = 0;
     for (auto& t : c->phase_ms) t = 0.0f;
+
     c->timing = (opts->flags & PDD_F_TIMING) != 0;
     c->progress = (opts->flags & PDD_F_PROGRESS) != 0;
     if (c->timing && !c->ev[0])
@@ -202,7 +206,7 @@ int pdd_decimate(pdd_ctx* ctx, const int32_t* d_xyz, int64_t n, int64_t keep_cou
 
 int pdd_last_stats(const pdd_ctx* ctx, int64_t* stats, int n) {
     if (!ctx || !stats || n < 0) return 0;
-    int m = n < 8 ? n : 8;
+    int m = n < 12 ? n : 12;
     for (int i = 0; i < m; i++) stats[i] = ctx->c.stats[i];
     return m;
 }
@@ -212,6 +216,68 @@ int pdd_last_timing(const pdd_ctx* ctx, float* ms, int n) {
     int m = n < pdd::kPhCount - 1 ? n : pdd::kPhCount - 1;
     for (int i = 0; i < m; i++) ms[i] = ctx->c.phase_ms[i];
     return m;
+}
+
+// ---------------------------------------------------------------------------
+// search-radius predictor
+// ---------------------------------------------------------------------------
+
+int pdd_pred_set_weights(pdd_ctx* ctx, const float* params, int64_t n) {
+    if (!ctx) return PDD_EINVAL;
+    if (hipSetDevice(ctx->c.device) != hipSuccess) return PDD_EHIP;
+    return pdd::pred_set(&ctx->c, params, n);
+}
+
+int pdd_pred_get_weights(pdd_ctx* ctx, float* params, int64_t n) {
+    if (!ctx) return PDD_EINVAL;
+    if (hipSetDevice(ctx->c.device) != hipSuccess) return PDD_EHIP;
+    return pdd::pred_get(&ctx->c, params, n);
+}
+
+int pdd_pred_enable(pdd_ctx* ctx, int32_t on, float margin_log2) {
+    if (!ctx || !(margin_log2 >= 0.0f && margin_log2 <= 8.0f)) return PDD_EINVAL;
+    if (on && !ctx->c.pred_ready) return PDD_EINVAL;
+    ctx->c.pred_on = on != 0;
+    ctx->c.pred_margin = margin_log2;
+    return PDD_OK;
+}
+
+int pdd_pred_samples(pdd_ctx* ctx, const pdd_grid* grid, int32_t k, int32_t b, uint16_t* d_feat, float* d_target,
+                     int64_t cap, int64_t* count) {
+    if (!ctx || !grid || !count || k < 1 || b < 0 || k + b > pdd::kMaxK || cap < 0) return PDD_EINVAL;
+    if (cap > 0 && (!d_feat || !d_target)) return PDD_EINVAL;
+    Ctx* c = &ctx->c;
+    if (hipSetDevice(c->device) != hipSuccess) return PDD_EHIP;
+    return pdd::pred_samples(c, grid->g.v, k, pdd::list_width(k + b), d_feat, d_target, cap, count);
+}
+
+int pdd_pred_forward(pdd_ctx* ctx, const uint16_t* d_feat, int64_t n, float* d_out) {
+    if (!ctx || n < 0 || (n > 0 && (!d_feat || !d_out))) return PDD_EINVAL;
+    Ctx* c = &ctx->c;
+    if (hipSetDevice(c->device) != hipSuccess) return PDD_EHIP;
+    int rc = pdd::pred_forward(c, d_feat, n, d_out);
+    if (rc) return rc;
+    PDD_HIP(c, hipStreamSynchronize(c->stream));
+    return PDD_OK;
+}
+
+int pdd_pred_grad(pdd_ctx* ctx, const uint16_t* d_feat, const float* d_target, int64_t n, float tau, float* d_grad,
+                  float* d_loss) {
+    if (!ctx || !d_feat || !d_target || !d_grad || !(tau > 0.0f && tau < 1.0f)) return PDD_EINVAL;
+    Ctx* c = &ctx->c;
+    if (hipSetDevice(c->device) != hipSuccess) return PDD_EHIP;
+    int rc = pdd::pred_grad(c, d_feat, d_target, n, tau, d_grad, d_loss);
+    if (rc) return rc;
+    PDD_HIP(c, hipStreamSynchronize(c->stream));
+    return PDD_OK;
+}
+
+int pdd_pred_train(pdd_ctx* ctx, const uint16_t* d_feat, const float* d_target, int64_t n, int32_t steps,
+                   int32_t batch, float lr, float tau, uint64_t seed, float* d_loss) {
+    if (!ctx || !d_feat || !d_target) return PDD_EINVAL;
+    Ctx* c = &ctx->c;
+    if (hipSetDevice(c->device) != hipSuccess) return PDD_EHIP;
+    return pdd::pred_train(c, d_feat, d_target, n, steps, batch, lr, tau, seed, d_loss);
 }
 
 }  // extern "C"

@@ -38,6 +38,17 @@ __host__ __device__ inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) 
     return spread21(x) | (spread21(y) << 1) | (spread21(z) << 2);
 }
 
+// inverse of spread21
+__host__ __device__ inline uint32_t compact21(uint64_t x) {
+    x &= 0x1249249249249249ull;
+    x = (x ^ (x >> 2)) & 0x10C30C30C30C30C3ull;
+    x = (x ^ (x >> 4)) & 0x100F00F00F00F00Full;
+    x = (x ^ (x >> 8)) & 0x1F0000FF0000FFull;
+    x = (x ^ (x >> 16)) & 0x1F00000000FFFFull;
+    x = (x ^ (x >> 32)) & 0x1FFFFFull;
+    return (uint32_t)x;
+}
+
 // exact squared distance of two int32 points whose per-axis difference is
 // below 2^21 in magnitude (extent check at grid build)
 __device__ inline uint64_t dist2(int ax, int ay, int az, int bx, int by, int bz) {
@@ -97,6 +108,7 @@ struct LevelView {
     const uint32_t* hvals;    // [hmask + 1] cell index
     const uint32_t* parent;   // [ncells] cell one level up (nullptr at the top level)
     const uint32_t* first0;   // [ncells + 1] first level-0 cell inside each cell (level 0: nullptr)
+    const uint64_t* key;      // [ncells] Morton code of each cell (coordinates at this level)
     uint32_t hmask;
     uint32_t ncells;
     uint32_t base;            // index of the level's first cell in the numbering of all levels' cells
@@ -150,7 +162,7 @@ struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
-    int64_t stats[8] = {0};
+    int64_t stats[12] = {0};
     // scratch pool: grow-only buffers keyed by slot
     struct Buf { void* p = nullptr; size_t bytes = 0; };
     Buf bufs[96];
@@ -160,6 +172,14 @@ struct Ctx {
     bool progress = false;    // PDD_F_PROGRESS: a line to stderr every 50 rounds
     hipEvent_t ev[8] = {};
     float phase_ms[8] = {0};
+    // search-radius predictor: fp32 parameters and Adam moments (device)
+    float* pred_P = nullptr;
+    float* pred_M = nullptr;
+    float* pred_V = nullptr;
+    int64_t pred_step = 0;
+    bool pred_ready = false;   // parameters set or trained
+    bool pred_on = false;      // the initial k-NN uses the predicted radius
+    float pred_margin = 0.25f; // added to the predicted log2 radius
 };
 
 // phase boundaries of a decimation, timed when PDD_F_TIMING is set

@@ -349,6 +349,7 @@ int build_grid(Ctx* c, const int32_t* xyz, int64_t n64, int stride, int voxel_lo
         lv.hkeys = L->hkeys;
         lv.hvals = L->hvals;
         lv.first0 = L->first0;
+        lv.key = L->key;
         lv.hmask = (uint32_t)(L->hcap - 1);
         lv.ncells = L->ncells;
         lv.s = sl;

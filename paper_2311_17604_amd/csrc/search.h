@@ -40,11 +40,11 @@ __device__ inline uint64_t face_gap2(int u, int cu, int r, int s, int cmax) {
     return g;
 }
 
-// Level at which a search around sorted point j starts: one below the
-// finest level whose cell around j holds at least `need` points (alive
-// points when alive_cnt, indexed by level base + cell, is given), so that the
-// 3x3x3 block there usually holds the neighbourhood.
-__device__ inline int start_level(const GridView& g, uint32_t j, uint32_t need, const uint32_t* alive_cnt) {
+// Anchor cell of sorted point j: the finest level L whose cell c around j
+// holds at least `need` points (alive points when alive_cnt, indexed by
+// level base + cell, is given), or the top level.
+__device__ inline void anchor_cell(const GridView& g, uint32_t j, uint32_t need, const uint32_t* alive_cnt, int* Lout,
+                                   uint32_t* cout) {
     uint32_t c = g.of0[j];
     int L = 0;
     for (;;) {
@@ -54,6 +54,16 @@ __device__ inline int start_level(const GridView& g, uint32_t j, uint32_t need, 
         c = lv.parent[c];
         L++;
     }
+    *Lout = L;
+    *cout = c;
+}
+
+// Level at which a search around sorted point j starts: one below its anchor
+// level, so that the 3x3x3 block there usually holds the neighbourhood.
+__device__ inline int start_level(const GridView& g, uint32_t j, uint32_t need, const uint32_t* alive_cnt) {
+    int L;
+    uint32_t c;
+    anchor_cell(g, j, need, alive_cnt, &L, &c);
     return L > 0 ? L - 1 : 0;
 }
 
@@ -94,11 +104,80 @@ __device__ inline void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Tests the points of up to 64 cells, one cell range [st, st + cnt) per lane,
+// against the wave's top-K list (lane j < K holds the j-th nearest).  Points
+// inside the previous level's block (skip; cell coordinates at shift ps
+// within 1 of (px, py, pz)) were tested already and are passed over.
+// Returns the number of points looked at (wave-uniform).
+template <int K, int MODE>
+__device__ inline uint32_t wave_scan(const GridView& g, uint32_t q, int4 qp, const SearchCtx& sc, uint32_t st,
+                                     uint32_t cnt, bool skip, int ps, int px, int py, int pz, uint64_t& my_d,
+                                     int32_t& my_id, uint32_t* lds_start, uint32_t* lds_excl) {
+    const int lane = (int)lane_id();
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_up((int)incl, o, kWave);
+        if (lane >= o) incl += v;
+    }
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+    if (total == 0) return 0;
+    lds_start[lane] = st;
+    lds_excl[lane] = incl - cnt;
+    wave_sync_lds();
+    for (uint32_t t0 = 0; t0 < total; t0 += kWave) {
+        const uint32_t t = t0 + (uint32_t)lane;
+        uint64_t d = ~0ull;
+        uint32_t j = 0;
+        if (t < total) {
+            int l = 0;
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1)
+                if (lds_excl[l + step] <= t) l += step;
+            const uint32_t pos = lds_start[l] + (t - lds_excl[l]);
+            const int4 p = g.pts[pos];
+            j = MODE == kAll ? pos : (uint32_t)p.w;
+            bool ok = j != q;
+            if (MODE != kAll && ok) ok = sc.alive[j] != 0;
+            if (ok && skip && abs(((p.x - g.minx) >> ps) - px) <= 1 && abs(((p.y - g.miny) >> ps) - py) <= 1 &&
+                abs(((p.z - g.minz) >> ps) - pz) <= 1)
+                ok = false;
+            if (ok) d = dist2(qp.x, qp.y, qp.z, p.x, p.y, p.z);
+        }
+        uint64_t thr = readlane64(my_d, K - 1);
+        uint64_t m = __ballot(d < thr);
+        while (m) {
+            const int l2 = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const uint64_t dv = readlane64(d, l2);
+            const int32_t iv = __builtin_amdgcn_readlane((int)j, l2);
+            const int p = __popcll(__ballot(lane < K && my_d <= dv));
+            if (p < K) {
+                const uint64_t upd = shfl_up64(my_d);
+                const int32_t upi = __shfl_up(my_id, 1, kWave);
+                if (lane == p) {
+                    my_d = dv;
+                    my_id = iv;
+                } else if (lane > p && lane < K) {
+                    my_d = upd;
+                    my_id = upi;
+                }
+                thr = readlane64(my_d, K - 1);
+                m &= __ballot(d < thr);
+            }
+        }
+    }
+    wave_sync_lds();
+    return total;
+}
+
 // lds_start / lds_excl: 64 entries of wave-private LDS each.  On return lane
-// j < K holds the j-th nearest (my_d = ~0 past the end).
+// j < K holds the j-th nearest (my_d = ~0 past the end).  *tested (if not
+// null) is increased by the number of points looked at.
 template <int K, int MODE>
 __device__ void wave_knn(const GridView& g, uint32_t q, int4 qp, const SearchCtx& sc, int kcert, int L0,
-                         uint64_t& my_d, int32_t& my_id, uint32_t* lds_start, uint32_t* lds_excl) {
+                         uint64_t& my_d, int32_t& my_id, uint32_t* lds_start, uint32_t* lds_excl,
+                         uint32_t* tested = nullptr) {
     const int lane = (int)lane_id();
     const int ux = qp.x - g.minx, uy = qp.y - g.miny, uz = qp.z - g.minz;
     my_d = ~0ull;
@@ -134,60 +213,9 @@ __device__ void wave_knn(const GridView& g, uint32_t q, int4 qp, const SearchCtx
                         }
                     }
                 }
-                uint32_t incl = cnt;
-#pragma unroll
-                for (int o = 1; o < kWave; o <<= 1) {
-                    const uint32_t v = (uint32_t)__shfl_up((int)incl, o, kWave);
-                    if (lane >= o) incl += v;
-                }
-                const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
-                if (total == 0) continue;
-                lds_start[lane] = st;
-                lds_excl[lane] = incl - cnt;
-                wave_sync_lds();
-                for (uint32_t t0 = 0; t0 < total; t0 += kWave) {
-                    const uint32_t t = t0 + (uint32_t)lane;
-                    uint64_t d = ~0ull;
-                    uint32_t j = 0;
-                    if (t < total) {
-                        int l = 0;
-#pragma unroll
-                        for (int step = 32; step > 0; step >>= 1)
-                            if (lds_excl[l + step] <= t) l += step;
-                        const uint32_t pos = lds_start[l] + (t - lds_excl[l]);
-                        const int4 p = g.pts[pos];
-                        j = MODE == kAll ? pos : (uint32_t)p.w;
-                        bool ok = j != q;
-                        if (MODE != kAll && ok) ok = sc.alive[j] != 0;
-                        if (ok && skip && abs(((p.x - g.minx) >> ps) - px) <= 1 &&
-                            abs(((p.y - g.miny) >> ps) - py) <= 1 && abs(((p.z - g.minz) >> ps) - pz) <= 1)
-                            ok = false;
-                        if (ok) d = dist2(qp.x, qp.y, qp.z, p.x, p.y, p.z);
-                    }
-                    uint64_t thr = readlane64(my_d, K - 1);
-                    uint64_t m = __ballot(d < thr);
-                    while (m) {
-                        const int l2 = __ffsll((unsigned long long)m) - 1;
-                        m &= m - 1;
-                        const uint64_t dv = readlane64(d, l2);
-                        const int32_t iv = __builtin_amdgcn_readlane((int)j, l2);
-                        const int p = __popcll(__ballot(lane < K && my_d <= dv));
-                        if (p < K) {
-                            const uint64_t upd = shfl_up64(my_d);
-                            const int32_t upi = __shfl_up(my_id, 1, kWave);
-                            if (lane == p) {
-                                my_d = dv;
-                                my_id = iv;
-                            } else if (lane > p && lane < K) {
-                                my_d = upd;
-                                my_id = upi;
-                            }
-                            thr = readlane64(my_d, K - 1);
-                            m &= __ballot(d < thr);
-                        }
-                    }
-                }
-                wave_sync_lds();
+                const uint32_t n = wave_scan<K, MODE>(g, q, qp, sc, st, cnt, skip, ps, px, py, pz, my_d, my_id,
+                                                      lds_start, lds_excl);
+                if (tested) *tested += n;
             }
             uint64_t g2 = face_gap2(ux, cx, r, s, lv.cmax[0]);
             const uint64_t gy = face_gap2(uy, cy, r, s, lv.cmax[1]);
@@ -200,6 +228,58 @@ __device__ void wave_knn(const GridView& g, uint32_t q, int4 qp, const SearchCtx
             if (kth != ~0ull && kth <= cert) return;
         }
     }
+}
+
+// Distance along one axis from coordinate u to the cell [c << s, (c+1) << s).
+__device__ inline uint64_t cell_gap(int u, int c, int s) {
+    const int lo = c << s, hi = ((c + 1) << s) - 1;
+    return (uint64_t)(u < lo ? lo - u : (u > hi ? u - hi : 0));
+}
+
+// Search bounded by a predicted ball: tests every point of the cells (at the
+// finest level whose edge is at least half the radius) that meet the ball of
+// squared radius r2 around the query.  True when the result is certified: the
+// kcert-th distance is within r2, so no untested point (all beyond r2) can be
+// nearer.  Otherwise the caller falls back to wave_knn.
+template <int K, int MODE>
+__device__ bool wave_knn_ball(const GridView& g, uint32_t q, int4 qp, const SearchCtx& sc, int kcert, uint64_t r2,
+                              uint64_t& my_d, int32_t& my_id, uint32_t* lds_start, uint32_t* lds_excl,
+                              uint32_t* tested = nullptr) {
+    const int lane = (int)lane_id();
+    const int ux = qp.x - g.minx, uy = qp.y - g.miny, uz = qp.z - g.minz;
+    my_d = ~0ull;
+    my_id = -1;
+    const int ri = (int)sqrt((double)r2) + 1;
+    int L = 0;
+    while (L + 1 < g.nlev && (2 << g.lv[L].s) < ri) L++;
+    const LevelView& lv = g.lv[L];
+    const int s = lv.s;
+    const int x0 = max((ux - ri) >> s, 0), x1 = min((ux + ri) >> s, lv.cmax[0]);
+    const int y0 = max((uy - ri) >> s, 0), y1 = min((uy + ri) >> s, lv.cmax[1]);
+    const int z0 = max((uz - ri) >> s, 0), z1 = min((uz + ri) >> s, lv.cmax[2]);
+    const int nx = x1 - x0 + 1, ny = y1 - y0 + 1, nz = z1 - z0 + 1;
+    const int nbox = nx * ny * nz;
+    for (int base = 0; base < nbox; base += kWave) {
+        const int idx = base + lane;
+        uint32_t st = 0, cnt = 0;
+        if (idx < nbox) {
+            const int x = x0 + idx % nx, y = y0 + (idx / nx) % ny, z = z0 + idx / (nx * ny);
+            const uint64_t gx = cell_gap(ux, x, s), gy = cell_gap(uy, y, s), gz = cell_gap(uz, z, s);
+            if (gx * gx + gy * gy + gz * gz <= r2) {
+                const uint32_t c =
+                    hash_find(lv.hkeys, lv.hvals, lv.hmask, morton3((uint32_t)x, (uint32_t)y, (uint32_t)z));
+                if (c != kNone) {
+                    st = lv.start[c];
+                    cnt = lv.start[c + 1] - st;
+                }
+            }
+        }
+        const uint32_t n =
+            wave_scan<K, MODE>(g, q, qp, sc, st, cnt, false, 0, 0, 0, 0, my_d, my_id, lds_start, lds_excl);
+        if (tested) *tested += n;
+    }
+    const uint64_t kth = readlane64(my_d, kcert - 1);
+    return kth != ~0ull && kth <= r2;
 }
 
 // Sum over lanes of v (wave-uniform result).

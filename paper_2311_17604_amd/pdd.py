@@ -18,8 +18,9 @@ PDD_F_TIMING = 2
 PDD_F_PROGRESS = 4
 PHASES = ("grid", "knn", "reverse", "rounds", "final")
 
-STATS = ("rounds", "researches", "rho_searches", "reverse_rebuilds", "knn_fallbacks", "voxel_log2",
-         "list_width", "touched")
+STATS = ("rounds", "researches", "danger_checks", "reverse_rebuilds", "unused4", "voxel_log2",
+         "list_width", "touched", "knn_tested", "pred_hits", "pred_misses", "unused11")
+PRED_NPARAM = 8385
 
 _lib = None
 
@@ -63,6 +64,17 @@ def load():
     lib.pdd_last_stats.restype = ctypes.c_int
     lib.pdd_last_timing.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
     lib.pdd_last_timing.restype = ctypes.c_int
+    f32 = ctypes.c_float
+    lib.pdd_pred_set_weights.argtypes = [P, P, i64]
+    lib.pdd_pred_get_weights.argtypes = [P, P, i64]
+    lib.pdd_pred_enable.argtypes = [P, i32, f32]
+    lib.pdd_pred_samples.argtypes = [P, P, i32, i32, P, P, i64, ctypes.POINTER(i64)]
+    lib.pdd_pred_forward.argtypes = [P, P, i64, P]
+    lib.pdd_pred_grad.argtypes = [P, P, P, i64, f32, P, P]
+    lib.pdd_pred_train.argtypes = [P, P, P, i64, i32, i32, f32, f32, ctypes.c_uint64, P]
+    for f in ("pdd_pred_set_weights", "pdd_pred_get_weights", "pdd_pred_enable", "pdd_pred_samples",
+              "pdd_pred_forward", "pdd_pred_grad", "pdd_pred_train"):
+        getattr(lib, f).restype = ctypes.c_int
     lib.pdd_strerror.argtypes = [ctypes.c_int]
     lib.pdd_strerror.restype = ctypes.c_char_p
     lib.pdd_last_error.argtypes = [P]
@@ -115,9 +127,9 @@ class Context:
         return {PHASES[i]: float(arr[i]) for i in range(n)}
 
     def stats(self) -> dict:
-        arr = (ctypes.c_int64 * 8)()
-        n = self.lib.pdd_last_stats(self.h, arr, 8)
-        return {STATS[i]: int(arr[i]) for i in range(n)}
+        arr = (ctypes.c_int64 * 12)()
+        n = self.lib.pdd_last_stats(self.h, arr, 12)
+        return {STATS[i]: int(arr[i]) for i in range(n) if not STATS[i].startswith("unused")}
 
 
 def _points(xyz):
@@ -178,3 +190,75 @@ def decimate(ctx: Context, xyz, keep: int, k: int, b: int = 0, voxel_log2: int =
     ctx._check(ctx.lib.pdd_decimate(ctx.h, _ptr(pts), n, keep, ctypes.byref(o), _ptr(kept), _ptr(order),
                                     _ptr(order_cost)), "pdd_decimate")
     return kept, order, order_cost
+
+
+# ---------------------------------------------------------------------------
+# search-radius predictor
+# ---------------------------------------------------------------------------
+
+def pred_set_weights(ctx: Context, params):
+    """Set the predictor's PRED_NPARAM fp32 parameters (numpy array)."""
+    import numpy as np
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    if a.shape != (PRED_NPARAM,):
+        raise ValueError("expected %d parameters" % PRED_NPARAM)
+    ctx._check(ctx.lib.pdd_pred_set_weights(ctx.h, a.ctypes.data_as(ctypes.c_void_p), a.size), "pdd_pred_set_weights")
+
+
+def pred_get_weights(ctx: Context):
+    import numpy as np
+    a = np.empty(PRED_NPARAM, dtype=np.float32)
+    ctx._check(ctx.lib.pdd_pred_get_weights(ctx.h, a.ctypes.data_as(ctypes.c_void_p), a.size), "pdd_pred_get_weights")
+    return a
+
+
+def pred_enable(ctx: Context, on: bool, margin_log2: float = 0.25):
+    ctx._check(ctx.lib.pdd_pred_enable(ctx.h, 1 if on else 0, margin_log2), "pdd_pred_enable")
+
+
+def pred_samples(ctx: Context, xyz, k: int, b: int = 0, voxel_log2: int = 0):
+    """Training rows of a cloud: (features [m, 64] int16 holding bf16 bits,
+    targets [m] float32), one row per anchor cell."""
+    import torch
+    pts, stride = _points(xyz)
+    n = pts.shape[0]
+    g = ctypes.c_void_p()
+    ctx._check(ctx.lib.pdd_build_grid(ctx.h, _ptr(pts), n, stride, voxel_log2, ctypes.byref(g)), "pdd_build_grid")
+    try:
+        cnt = ctypes.c_int64()
+        ctx._check(ctx.lib.pdd_pred_samples(ctx.h, g, k, b, None, None, 0, ctypes.byref(cnt)), "pdd_pred_samples")
+        m = int(cnt.value)
+        feat = torch.empty((max(m, 1), 64), dtype=torch.int16, device=pts.device)
+        tgt = torch.empty(max(m, 1), dtype=torch.float32, device=pts.device)
+        ctx._check(ctx.lib.pdd_pred_samples(ctx.h, g, k, b, _ptr(feat), _ptr(tgt), m, ctypes.byref(cnt)),
+                   "pdd_pred_samples")
+    finally:
+        ctx.lib.pdd_grid_free(ctx.h, g)
+    return feat[:m], tgt[:m]
+
+
+def pred_forward(ctx: Context, feat):
+    import torch
+    out = torch.empty(feat.shape[0], dtype=torch.float32, device=feat.device)
+    ctx._check(ctx.lib.pdd_pred_forward(ctx.h, _ptr(feat), feat.shape[0], _ptr(out)), "pdd_pred_forward")
+    return out
+
+
+def pred_grad(ctx: Context, feat, target, tau: float):
+    """(gradient [PRED_NPARAM] float32, loss) over all rows (at most 128)."""
+    import torch
+    grad = torch.empty(PRED_NPARAM, dtype=torch.float32, device=feat.device)
+    loss = torch.empty(1, dtype=torch.float32, device=feat.device)
+    ctx._check(ctx.lib.pdd_pred_grad(ctx.h, _ptr(feat), _ptr(target), feat.shape[0], tau, _ptr(grad), _ptr(loss)),
+               "pdd_pred_grad")
+    return grad, float(loss.item())
+
+
+def pred_train(ctx: Context, feat, target, steps: int, batch: int = 128, lr: float = 1e-3, tau: float = 0.9,
+               seed: int = 1):
+    """Adam steps on the context's predictor; returns the per-step losses."""
+    import torch
+    loss = torch.empty(max(steps, 1), dtype=torch.float32, device=feat.device)
+    ctx._check(ctx.lib.pdd_pred_train(ctx.h, _ptr(feat), _ptr(target), feat.shape[0], steps, batch, lr, tau, seed,
+                                      _ptr(loss)), "pdd_pred_train")
+    return loss[:steps]
