@@ -133,6 +133,30 @@ int pdd_knn_cost(pdd_ctx *ctx, const pdd_grid *grid, int32_t k, int32_t b, int32
 int pdd_decimate(pdd_ctx *ctx, const int32_t *d_xyz, int64_t n, int64_t keep_count,
                  const pdd_opts *opts, int32_t *d_kept, int32_t *d_order, uint64_t *d_order_cost);
 
+/*
+ * Batch of independent clouds (scans) decimated together: cloud s is
+ * points [h_offsets[s], h_offsets[s+1]) of d_xyz and keeps h_keep[s] of them,
+ * exactly as pdd_decimate would on that cloud alone (Sec. 3 and 4 per
+ * cloud).  All clouds share one grid (the cloud is the top of the sort key,
+ * so no neighbourhood crosses two clouds) and one set of round kernels; in
+ * each round every cloud whose ranked set exceeds its remaining removals
+ * keeps only its top keys.
+ *   h_offsets   : host array of nscan + 1 offsets, h_offsets[0] = 0,
+ *                 every cloud at least 2 points, total < 2^31
+ *   h_keep      : host array of nscan counts, 1 <= h_keep[s] <= size of s
+ *   d_kept      : [sum h_keep] int32: per cloud its kept indices (relative to
+ *                 the cloud's first point), ascending, clouds in order
+ *   d_order     : [sum (size - keep)] int32 or NULL: per cloud its removed
+ *                 indices (relative) in removal order, clouds in order
+ *   d_order_cost: [sum (size - keep)] uint64 or NULL: cost at removal
+ * Each cloud's extent must fit 2^b mm per axis and the clouds 2^c ids with
+ * 3b + c <= 63 (else PDD_ERANGE).  Synchronises the stream.
+ * Errors: PDD_EINVAL, PDD_ERANGE, PDD_ENOMEM, PDD_EHIP, PDD_EINTERNAL.
+ */
+int pdd_decimate_batch(pdd_ctx *ctx, const int32_t *d_xyz, const int64_t *h_offsets, int32_t nscan,
+                       const int64_t *h_keep, const pdd_opts *opts, int32_t *d_kept, int32_t *d_order,
+                       uint64_t *d_order_cost);
+
 /* Counters of the last pdd_decimate on this context, written to stats[0..n),
  * n <= 12:
  *   0 rounds, 1 re-searches (buffer exhausted), 2 danger checks, 3 reverse-list

@@ -6,8 +6,8 @@
 
 namespace pdd {
 
-int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, int64_t keep, int32_t* kept,
-             int32_t* order, uint64_t* order_cost);
+int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, const int64_t* h_off,
+             const int64_t* h_keep, int nseg, int32_t* kept, int32_t* order, uint64_t* order_cost);
 
 int hip_fail(Ctx* c, hipError_t e, const char* what) {
     if (c) c->err = std::string(what) + ": " + hipGetErrorString(e);
@@ -16,7 +16,7 @@ int hip_fail(Ctx* c, hipError_t e, const char* what) {
 }
 
 void* scratch(Ctx* c, int slot, size_t bytes) {
-    if (slot < 0 || slot >= 96) return nullptr;
+    if (slot < 0 || slot >= kScratchSlots) return nullptr;
     Ctx::Buf& b = c->bufs[slot];
     if (b.bytes >= bytes && b.p) return b.p;
     if (b.p) {
@@ -162,10 +162,8 @@ int pdd_knn_cost(pdd_ctx* ctx, const pdd_grid* grid, int32_t k, int32_t b, int32
     return pdd::knn_to_original(c, g, K, k + b, ko, d_nbr, d_r2k, d_cost);
 }
 
-int pdd_decimate(pdd_ctx* ctx, const int32_t* d_xyz, int64_t n, int64_t keep_count, const pdd_opts* opts,
-                 int32_t* d_kept, int32_t* d_order, uint64_t* d_order_cost) {
-    if (!ctx || !d_xyz || !opts || !d_kept || n < 2 || n >= (int64_t)0x7FFFFFFF) return PDD_EINVAL;
-    if (keep_count < 1 || keep_count > n) return PDD_EINVAL;
+static int decimate_common(pdd_ctx* ctx, const int32_t* d_xyz, int64_t n, const int64_t* h_off, const int64_t* h_keep,
+                           int nseg, const pdd_opts* opts, int32_t* d_kept, int32_t* d_order, uint64_t* d_order_cost) {
     const int k = opts->k;
     if (k < 1 || k > pdd::kMaxK) return PDD_EINVAL;
     int b = opts->b;
@@ -181,7 +179,6 @@ int pdd_decimate(pdd_ctx* ctx, const int32_t* d_xyz, int64_t n, int64_t keep_cou
     if (hipSetDevice(c->device) != hipSuccess) return PDD_EHIP;
     for (auto& s : c->stats) s = 0;
     for (auto& t : c->phase_ms) t = 0.0f;
-
     c->timing = (opts->flags & PDD_F_TIMING) != 0;
     c->progress = (opts->flags & PDD_F_PROGRESS) != 0;
     if (c->timing && !c->ev[0])
@@ -189,19 +186,42 @@ int pdd_decimate(pdd_ctx* ctx, const int32_t* d_xyz, int64_t n, int64_t keep_cou
             if (hipEventCreate(&e) != hipSuccess) return PDD_EHIP;
     pdd::mark(c, pdd::kPhStart);
     pdd::Grid grid;
-    int rc = pdd::build_grid(c, d_xyz, n, stride, opts->voxel_log2, &grid);
+    int rc = pdd::build_grid_seg(c, d_xyz, n, stride, opts->voxel_log2, h_off, nseg, &grid);
     if (rc == PDD_OK) {
         const int K = pdd::list_width(k + b);
         c->stats[5] = grid.v.lv[0].s;
         c->stats[6] = K;
-        rc = pdd::decimate(c, grid, k, K, frac, (opts->flags & PDD_F_CHECK) ? 1 : 0, keep_count, d_kept, d_order,
-                           d_order_cost);
+        rc = pdd::decimate(c, grid, k, K, frac, (opts->flags & PDD_F_CHECK) ? 1 : 0, h_off, h_keep, nseg, d_kept,
+                           d_order, d_order_cost);
     }
     (void)hipStreamSynchronize(c->stream);
     if (rc == PDD_OK && c->timing)
         for (int i = 1; i < pdd::kPhCount; i++) (void)hipEventElapsedTime(&c->phase_ms[i - 1], c->ev[i - 1], c->ev[i]);
     pdd::free_grid(&grid);
     return rc;
+}
+
+int pdd_decimate(pdd_ctx* ctx, const int32_t* d_xyz, int64_t n, int64_t keep_count, const pdd_opts* opts,
+                 int32_t* d_kept, int32_t* d_order, uint64_t* d_order_cost) {
+    if (!ctx || !d_xyz || !opts || !d_kept || n < 2 || n >= (int64_t)0x7FFFFFFF) return PDD_EINVAL;
+    if (keep_count < 1 || keep_count > n) return PDD_EINVAL;
+    const int64_t off[2] = {0, n};
+    return decimate_common(ctx, d_xyz, n, off, &keep_count, 1, opts, d_kept, d_order, d_order_cost);
+}
+
+int pdd_decimate_batch(pdd_ctx* ctx, const int32_t* d_xyz, const int64_t* h_offsets, int32_t nscan,
+                       const int64_t* h_keep, const pdd_opts* opts, int32_t* d_kept, int32_t* d_order,
+                       uint64_t* d_order_cost) {
+    if (!ctx || !d_xyz || !h_offsets || !h_keep || !opts || !d_kept || nscan < 1 || nscan > (1 << 20))
+        return PDD_EINVAL;
+    if (h_offsets[0] != 0) return PDD_EINVAL;
+    for (int s = 0; s < nscan; s++) {
+        const int64_t ns = h_offsets[s + 1] - h_offsets[s];
+        if (ns < 2 || h_keep[s] < 1 || h_keep[s] > ns) return PDD_EINVAL;
+    }
+    const int64_t n = h_offsets[nscan];
+    if (n >= (int64_t)0x7FFFFFFF) return PDD_EINVAL;
+    return decimate_common(ctx, d_xyz, n, h_offsets, h_keep, nscan, opts, d_kept, d_order, d_order_cost);
 }
 
 int pdd_last_stats(const pdd_ctx* ctx, int64_t* stats, int n) {

@@ -163,16 +163,23 @@ __global__ void __launch_bounds__(kBlock) rb_survive(RoundArrays a, GridView g) 
             if ((threadIdx.x & (kWave - 1)) == 0 && v != ~0ull)
                 atomicMin((unsigned long long*)&st->surv_min[j], (unsigned long long)v);
         }
-        // highest cost of A (wave maximum, one atomic per wave)
+        // highest cost of each segment's A (wave maximum when the wave's A
+        // points share one segment, one atomic per wave)
+        const uint32_t sx = t < nA ? seg_of_pt(a, x) : 0u;
+        const uint32_t s0 = (uint32_t)__shfl((int)sx, 0, kWave);
+        if (__all(t >= nA || sx == s0)) {
 #pragma unroll
-        for (int o = kWave / 2; o > 0; o >>= 1) {
-            const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)cmax, o, kWave);
-            const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(cmax >> 32), o, kWave);
-            const uint64_t v = ((uint64_t)hi << 32) | lo;
-            cmax = v > cmax ? v : cmax;
+            for (int o = kWave / 2; o > 0; o >>= 1) {
+                const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)cmax, o, kWave);
+                const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(cmax >> 32), o, kWave);
+                const uint64_t v = ((uint64_t)hi << 32) | lo;
+                cmax = v > cmax ? v : cmax;
+            }
+            if ((threadIdx.x & (kWave - 1)) == 0 && cmax)
+                atomicMax((unsigned long long*)&a.seg_top_cost[s0], (unsigned long long)cmax);
+        } else if (t < nA && cmax) {
+            atomicMax((unsigned long long*)&a.seg_top_cost[sx], (unsigned long long)cmax);
         }
-        if ((threadIdx.x & (kWave - 1)) == 0 && cmax)
-            atomicMax((unsigned long long*)&st->top_cost, (unsigned long long)cmax);
     }
 }
 
@@ -188,11 +195,13 @@ __global__ void __launch_bounds__(kBlock) rb_bucket(RoundArrays a) {
         const uint32_t c = a.of0[x];
         a.surv_bucket[a.surv_off[c] + atomicSub(&a.cS[c], 1u) - 1u] = x;
     }
-    // the highest key of A survives every condition; find its index
+    // the highest key of each segment's A survives every condition; find
+    // its index
     const uint32_t nA = st->nA;
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nA; t += gridDim.x * blockDim.x) {
         const uint32_t x = a.A[t];
-        if (a.cost[x] == st->top_cost) atomicMin(&st->top_orig, a.pts[x].w);
+        const uint32_t sx = seg_of_pt(a, x);
+        if (a.cost[x] == a.seg_top_cost[sx]) atomicMin(&a.seg_top_orig[sx], a.pts[x].w);
     }
 }
 
@@ -210,8 +219,8 @@ __device__ inline uint64_t block_reach2(int u, int c, int r, int s) {
 // the first block, over shells 0 and 1 of the levels from L1 up, whose cells
 // hold k such points by the per-cell counts.  0 where even the top block
 // (the whole cloud) holds fewer.
-__device__ void level_bounds(const GridView& g, const RoundArrays& a, int ux, int uy, int uz, int L1, uint32_t want,
-                             int k, uint64_t* R2) {
+__device__ void level_bounds(const GridView& g, const RoundArrays& a, uint32_t ys, int ux, int uy, int uz, int L1,
+                             uint32_t want, int k, uint64_t* R2) {
     const int lane = (int)lane_id();
 #pragma unroll
     for (int j = 0; j < kLev; j++) R2[j] = 0;
@@ -225,8 +234,7 @@ __device__ void level_bounds(const GridView& g, const RoundArrays& a, int ux, in
         if (lane < 27) {
             const int x = cx + lane % 3 - 1, y = cy + (lane / 3) % 3 - 1, z = cz + lane / 9 - 1;
             if (x >= 0 && y >= 0 && z >= 0 && x <= lv.cmax[0] && y <= lv.cmax[1] && z <= lv.cmax[2]) {
-                const uint32_t c =
-                    hash_find(lv.hkeys, lv.hvals, lv.hmask, morton3((uint32_t)x, (uint32_t)y, (uint32_t)z));
+                const uint32_t c = hash_find(lv.hkeys, lv.hvals, lv.hmask, cell_code(lv, ys, x, y, z));
                 if (c != kNone) {
                     const size_t gc = lv.base + c;
                     uint32_t la[kLev], inA = 0;
@@ -274,8 +282,8 @@ __device__ inline uint64_t axis_gap(int u, int c, int s) {
 // of alive points not above x within d(x, y) of y reaches k: the entries of
 // y's list not above x, plus entries of x's own list that lie beyond y's
 // list radius and within d(x, y).  When no R_j is found, every survivor of
-// level j at or below min(key(y), threshold) waits (cost bound in
-// glob_block, applied at removal).
+// level j at or below min(key(y), threshold) in y's segment waits (cost
+// bound in seg_glob, applied at removal).
 template <int K>
 __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
     RoundDev* st = a.st;
@@ -336,6 +344,7 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
             if (__popcll(__ballot(lcls != 0 && llev < j)) >= k) risk &= ~(1u << j);
         if (!risk) continue;
         const int ux = py.x - g.minx, uy = py.y - g.miny, uz = py.z - g.minz;
+        const uint32_t ys = seg_at(g, y);
         // R2[j] (0 = none found) for the key levels at risk, from the finest
         // level whose 3x3x3 block can reach beyond y's list radius (the
         // list holds every alive point nearer than dlast, fewer than k of
@@ -346,13 +355,13 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
             int sneed = 0;
             while (sneed < 21 && (12ull << (2 * sneed)) < dlast) sneed++;
             const int L1 = min(max(sneed - g.lv[0].s, 0), g.nlev - 1);
-            level_bounds(g, a, ux, uy, uz, L1, risk, k, R2);
+            level_bounds(g, a, ys, ux, uy, uz, L1, risk, k, R2);
             const uint64_t cb = (cy < tc ? cy : tc) + 1;
 #pragma unroll
             for (int j = 0; j < kLev; j++) {
                 if (!((risk >> j) & 1u)) continue;
                 if (R2[j] == 0) {
-                    if (lane == 0) atomicMax((unsigned long long*)&st->glob_block[j], (unsigned long long)cb);
+                    if (lane == 0) atomicMax((unsigned long long*)&a.seg_glob[ys * kLev + j], (unsigned long long)cb);
                 } else if (R2[j] > rbox) {
                     rbox = R2[j];
                 }
@@ -411,8 +420,7 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
                     // skip cells wholly at squared distance >= rbox
                     const uint64_t gx = axis_gap(ux, xx, sc), gy = axis_gap(uy, yy, sc), gz = axis_gap(uz, zz, sc);
                     if (gx * gx + gy * gy + gz * gz < rbox) {
-                        const uint32_t c = hash_find(lv.hkeys, lv.hvals, lv.hmask,
-                                                     morton3((uint32_t)xx, (uint32_t)yy, (uint32_t)zz));
+                        const uint32_t c = hash_find(lv.hkeys, lv.hvals, lv.hmask, cell_code(lv, ys, xx, yy, zz));
                         if (c != kNone) {
                             const uint32_t f0 = lv.first0 ? lv.first0[c] : c;
                             const uint32_t f1 = lv.first0 ? lv.first0[c + 1] : c + 1;

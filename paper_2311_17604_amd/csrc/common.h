@@ -18,6 +18,7 @@ constexpr uint64_t kEmptyKey = ~0ull;
 constexpr int kSelBins0 = 4160;     // first-level bins of the threshold select (65 * 64)
 constexpr int kSelBins = 4096;      // refinement bins (12-bit digits)
 constexpr int kSelFinal = 2048;     // candidates resolved by one block sort
+constexpr int kScratchSlots = 128;  // scratch buffers of a context
 
 // ---------------------------------------------------------------------------
 // small device helpers
@@ -112,23 +113,36 @@ struct LevelView {
     uint32_t hmask;
     uint32_t ncells;
     uint32_t base;            // index of the level's first cell in the numbering of all levels' cells
-    int32_t cmax[3];          // largest cell coordinate per axis
+    int32_t cmax[3];          // largest cell coordinate per axis (over all segments)
     int32_t s;
-    int32_t pad;
+    int32_t segshift;         // cell code = segment << segshift | Morton code of the cell coordinates
 };
+
+// hash key of cell (x, y, z) of segment sg at a level
+__device__ inline uint64_t cell_code(const LevelView& lv, uint32_t sg, int x, int y, int z) {
+    return ((uint64_t)sg << lv.segshift) | morton3((uint32_t)x, (uint32_t)y, (uint32_t)z);
+}
 
 // The grid: points in Morton order with their original index, and a stack
 // of cell levels with edges 2^s0, 2^(s0+1), ... up to one whose 3x3x3 block
-// covers the cloud.
+// covers the cloud.  A grid may hold several independent clouds
+// (segments): the segment is the top of the sort key, so each segment's
+// points are contiguous and cells never span two segments; coordinates are
+// relative to the segment's minimum corner.
 struct GridView {
-    const int4* pts;          // [n] x, y, z, original index
+    const int4* pts;          // [n] x, y, z (relative to the segment's corner), original index
     const uint32_t* of0;      // [n] level-0 cell of each sorted point
+    const uint32_t* seg;      // [n] segment of each sorted point (nullptr: one segment)
     uint32_t n;
     uint32_t total_cells;     // cells over all levels
-    int32_t minx, miny, minz;
-    int32_t nlev;             // >= 2
+    int32_t minx, miny, minz; // 0: coordinates are already relative
+    int32_t nlev;             // >= 1
+    int32_t nseg;
+    int32_t bits_axis;        // bits per axis of the Morton codes
     LevelView lv[kMaxLevels];
 };
+
+__device__ inline uint32_t seg_at(const GridView& g, uint32_t j) { return g.seg ? g.seg[j] : 0u; }
 
 // level-l cell of a level-0 cell
 __device__ inline uint32_t cell_up(const GridView& g, uint32_t c0, int l) {
@@ -151,6 +165,7 @@ struct Grid {
     GridView v;
     int4* pts = nullptr;
     uint32_t* of0 = nullptr;
+    uint32_t* seg = nullptr;
     Level lev[kMaxLevels];
 };
 
@@ -165,7 +180,7 @@ struct Ctx {
     int64_t stats[12] = {0};
     // scratch pool: grow-only buffers keyed by slot
     struct Buf { void* p = nullptr; size_t bytes = 0; };
-    Buf bufs[96];
+    Buf bufs[kScratchSlots];
     void* pinned = nullptr;   // small pinned host buffer for status read-back
     // phase timing (PDD_F_TIMING): events recorded on the context's stream
     bool timing = false;
@@ -208,6 +223,9 @@ int iota_u32(Ctx* c, uint32_t* p, uint32_t count);
 
 // grid (grid.hip)
 int build_grid(Ctx* c, const int32_t* xyz, int64_t n, int stride, int voxel_log2, Grid* g);
+// several clouds at once: cloud s is points [h_off[s], h_off[s + 1]) (host array)
+int build_grid_seg(Ctx* c, const int32_t* xyz, int64_t n, int stride, int voxel_log2, const int64_t* h_off, int nseg,
+                   Grid* g);
 void free_grid(Grid* g);
 
 // k-NN (knn.hip)

@@ -5,62 +5,116 @@
 // sorted by the Morton code of their coordinates relative to the minimum
 // corner, so every voxel (and every coarser Morton cell) is a contiguous run
 // of the sorted array.
+#include <vector>
+
 #include "common.h"
 
 namespace pdd {
 
 namespace {
 
-__global__ void bounds_init(int32_t* b) {
-    if (threadIdx.x < 3) b[threadIdx.x] = INT32_MAX;
-    else if (threadIdx.x < 6) b[threadIdx.x] = INT32_MIN;
+__global__ void __launch_bounds__(kBlock) bounds_init(int32_t* b, int nseg) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 6 * nseg; i += gridDim.x * blockDim.x)
+        b[i] = (i % 6) < 3 ? INT32_MAX : INT32_MIN;
+}
+
+// segment of input point i: the last s with off[s] <= i
+__device__ inline uint32_t seg_of(const int64_t* __restrict__ off, int nseg, uint64_t i) {
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int m = (lo + hi + 1) >> 1;
+        if ((uint64_t)off[m] <= i) lo = m; else hi = m - 1;
+    }
+    return (uint32_t)lo;
+}
+
+// per-segment minimum and maximum of each axis, b[6 s + a]: each thread
+// takes a run of kBoundsRun points, keeps running bounds while the segment
+// stays the same, and flushes them with atomics (wave-reduced when the whole
+// wave ends in one segment)
+constexpr int kBoundsRun = 256;
+
+__device__ inline void bounds_flush(int32_t* b, uint32_t sg, const int32_t* mn, const int32_t* mx) {
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        atomicMin(&b[6 * sg + a], mn[a]);
+        atomicMax(&b[6 * sg + 3 + a], mx[a]);
+    }
 }
 
 __global__ void __launch_bounds__(kBlock) bounds_k(const int32_t* __restrict__ xyz, uint32_t n, int sw,
-                                                   int32_t* __restrict__ b) {
+                                                   const int64_t* __restrict__ off, int nseg, int32_t* __restrict__ b) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i0 = t * kBoundsRun, i1 = min(i0 + kBoundsRun, (uint64_t)n);
     int32_t mn[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, mx[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    uint32_t sg = 0;
+    uint64_t seg_end = ~0ull;
+    if (i0 < i1 && nseg > 1) {
+        sg = seg_of(off, nseg, i0);
+        seg_end = (uint64_t)off[sg + 1];
+    }
+    for (uint64_t i = i0; i < i1; i++) {
+        if (i >= seg_end) {
+            bounds_flush(b, sg, mn, mx);
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                mn[a] = INT32_MAX;
+                mx[a] = INT32_MIN;
+            }
+            while (i >= (uint64_t)off[sg + 1]) sg++;
+            seg_end = (uint64_t)off[sg + 1];
+        }
         const int32_t* p = xyz + i * sw;
 #pragma unroll
         for (int a = 0; a < 3; a++) {
-            int32_t v = p[a];
-            mn[a] = min(mn[a], v);
-            mx[a] = max(mx[a], v);
+            mn[a] = min(mn[a], p[a]);
+            mx[a] = max(mx[a], p[a]);
         }
     }
+    // threads without points hold the identities; they join any segment
+    const bool has = i0 < i1;
+    const uint32_t s0 = (uint32_t)__shfl((int)sg, 0, kWave);
+    if (__all(!has || sg == s0)) {
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-        for (int o = kWave / 2; o > 0; o >>= 1) {
-            mn[a] = min(mn[a], __shfl_xor(mn[a], o, kWave));
-            mx[a] = max(mx[a], __shfl_xor(mx[a], o, kWave));
-        }
-    }
-    if ((threadIdx.x & (kWave - 1)) == 0) {
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            atomicMin(&b[a], mn[a]);
-            atomicMax(&b[3 + a], mx[a]);
-        }
+        for (int a = 0; a < 3; a++)
+            for (int o = kWave / 2; o > 0; o >>= 1) {
+                mn[a] = min(mn[a], __shfl_xor(mn[a], o, kWave));
+                mx[a] = max(mx[a], __shfl_xor(mx[a], o, kWave));
+            }
+        if ((threadIdx.x & (kWave - 1)) == 0 && __shfl((int)has, 0, kWave)) bounds_flush(b, s0, mn, mx);
+    } else if (has) {
+        bounds_flush(b, sg, mn, mx);
     }
 }
 
-__global__ void __launch_bounds__(kBlock) morton_k(const int32_t* __restrict__ xyz, uint32_t n, int sw, int32_t mx,
-                                                   int32_t my, int32_t mz, uint64_t* __restrict__ keys,
-                                                   uint32_t* __restrict__ vals) {
+// key = segment << 3 bits_axis | Morton code of the coordinates relative to
+// the segment's minimum corner
+__global__ void __launch_bounds__(kBlock) morton_k(const int32_t* __restrict__ xyz, uint32_t n, int sw,
+                                                   const int64_t* __restrict__ off, int nseg,
+                                                   const int32_t* __restrict__ b, int bits_axis,
+                                                   uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const int32_t* p = xyz + i * sw;
-        keys[i] = morton3((uint32_t)(p[0] - mx), (uint32_t)(p[1] - my), (uint32_t)(p[2] - mz));
+        const uint32_t sg = nseg > 1 ? seg_of(off, nseg, i) : 0u;
+        const int32_t* m = b + 6 * sg;
+        keys[i] = ((uint64_t)sg << (3 * bits_axis)) |
+                  morton3((uint32_t)(p[0] - m[0]), (uint32_t)(p[1] - m[1]), (uint32_t)(p[2] - m[2]));
         vals[i] = (uint32_t)i;
     }
 }
 
+// sorted points in coordinates relative to their segment's minimum corner
 __global__ void __launch_bounds__(kBlock) permute_k(const int32_t* __restrict__ xyz, int sw,
-                                                    const uint32_t* __restrict__ vals, uint32_t n,
-                                                    int4* __restrict__ pts) {
+                                                    const uint64_t* __restrict__ sk, const uint32_t* __restrict__ vals,
+                                                    uint32_t n, int bits_axis, const int32_t* __restrict__ b,
+                                                    int4* __restrict__ pts, uint32_t* __restrict__ seg) {
     for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (size_t)gridDim.x * blockDim.x) {
-        uint32_t o = vals[j];
+        const uint32_t o = vals[j];
+        const uint32_t sg = (uint32_t)(sk[j] >> (3 * bits_axis));
         const int32_t* p = xyz + (size_t)o * sw;
-        pts[j] = make_int4(p[0], p[1], p[2], (int)o);
+        const int32_t* m = b + 6 * sg;
+        pts[j] = make_int4(p[0] - m[0], p[1] - m[1], p[2] - m[2], (int)o);
+        if (seg) seg[j] = sg;
     }
 }
 
@@ -175,7 +229,7 @@ inline unsigned grid_for(size_t count, unsigned maxg = 16384) {
 }
 
 // scratch slots used while building a grid
-enum { kSlotBounds = 0, kSlotKeys = 1, kSlotVals = 2, kSlotFlag = 3, kSlotPos = 4, kSlotLev = 5, kSlotOcc = 6 };
+enum { kSlotBounds = 0, kSlotKeys = 1, kSlotVals = 2, kSlotFlag = 3, kSlotPos = 4, kSlotOff = 5, kSlotOcc = 6 };
 
 }  // namespace
 
@@ -192,6 +246,7 @@ static void free_level(Level* l) {
 void free_grid(Grid* g) {
     if (g->pts) (void)hipFree(g->pts);
     if (g->of0) (void)hipFree(g->of0);
+    if (g->seg) (void)hipFree(g->seg);
     for (auto& l : g->lev) free_level(&l);
     *g = Grid();
 }
@@ -235,7 +290,7 @@ static int build_hash(Ctx* c, Level* l) {
 // of the points (occupancy seen from the points, which is what a search
 // pays), so that the densest regions still get small cells; coarser regions
 // use the levels above.
-static int choose_finest(Ctx* c, const uint64_t* sk, uint32_t n, int* s_out) {
+static int choose_finest(Ctx* c, const uint64_t* sk, uint32_t n, int smax, int* s_out) {
     uint32_t* hist = (uint32_t*)scratch(c, kSlotOcc, 22 * 32 * 4);
     if (!hist) return PDD_ENOMEM;
     int rc;
@@ -247,7 +302,7 @@ static int choose_finest(Ctx* c, const uint64_t* sk, uint32_t n, int* s_out) {
     PDD_HIP(c, hipMemcpyAsync(h, hist, 22 * 32 * 4, hipMemcpyDeviceToHost, c->stream));
     PDD_HIP(c, hipStreamSynchronize(c->stream));
     int best = 0;
-    for (int s = 0; s < 22; s++) {
+    for (int s = 0; s <= smax; s++) {
         // 90th percentile bin of the counts
         uint32_t acc = 0;
         int p90 = 31;
@@ -266,56 +321,75 @@ static int choose_finest(Ctx* c, const uint64_t* sk, uint32_t n, int* s_out) {
 }
 
 int build_grid(Ctx* c, const int32_t* xyz, int64_t n64, int stride, int voxel_log2, Grid* g) {
+    const int64_t off[2] = {0, n64};
+    return build_grid_seg(c, xyz, n64, stride, voxel_log2, off, 1, g);
+}
+
+int build_grid_seg(Ctx* c, const int32_t* xyz, int64_t n64, int stride, int voxel_log2, const int64_t* h_off, int nseg,
+                   Grid* g) {
     *g = Grid();
-    if (n64 < 2 || n64 >= (int64_t)0x7FFFFFFF || (stride != 12 && stride != 16)) return PDD_EINVAL;
+    if (n64 < 2 || n64 >= (int64_t)0x7FFFFFFF || (stride != 12 && stride != 16) || nseg < 1) return PDD_EINVAL;
     if (voxel_log2 != 0 && (voxel_log2 < 2 || voxel_log2 > 20)) return PDD_EINVAL;
     const uint32_t n = (uint32_t)n64;
     const int sw = stride / 4;
-    int32_t* bnd = (int32_t*)scratch(c, kSlotBounds, 64);
+    int32_t* bnd = (int32_t*)scratch(c, kSlotBounds, (size_t)nseg * 6 * 4);
+    int64_t* doff = (int64_t*)scratch(c, kSlotOff, (size_t)(nseg + 1) * 8);
     uint64_t* keys = (uint64_t*)scratch(c, kSlotKeys, (size_t)n * 8);
     uint32_t* vals = (uint32_t*)scratch(c, kSlotVals, (size_t)n * 4);
     uint32_t* flag = (uint32_t*)scratch(c, kSlotFlag, (size_t)n * 4);
     uint32_t* pos = (uint32_t*)scratch(c, kSlotPos, (size_t)(n + 1) * 4);
-    if (!bnd || !keys || !vals || !flag || !pos) return PDD_ENOMEM;
-    int32_t* hb = (int32_t*)c->pinned;
+    if (!bnd || !doff || !keys || !vals || !flag || !pos) return PDD_ENOMEM;
 
-    hipLaunchKernelGGL(bounds_init, dim3(1), dim3(64), 0, c->stream, bnd);
-    hipLaunchKernelGGL(bounds_k, dim3(grid_for(n, 2048)), dim3(kBlock), 0, c->stream, xyz, n, sw, bnd);
+    PDD_HIP(c, hipMemcpyAsync(doff, h_off, (size_t)(nseg + 1) * 8, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(bounds_init, dim3(grid_for((size_t)nseg * 6)), dim3(kBlock), 0, c->stream, bnd, nseg);
+    const size_t nthreads = ((size_t)n + kBoundsRun - 1) / kBoundsRun;
+    hipLaunchKernelGGL(bounds_k, dim3((unsigned)((nthreads + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, xyz, n,
+                       sw, doff, nseg, bnd);
     PDD_HIP(c, hipGetLastError());
-    PDD_HIP(c, hipMemcpyAsync(hb, bnd, 6 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    std::vector<int32_t> hb((size_t)nseg * 6);
+    PDD_HIP(c, hipMemcpyAsync(hb.data(), bnd, hb.size() * 4, hipMemcpyDeviceToHost, c->stream));
     PDD_HIP(c, hipStreamSynchronize(c->stream));
-    int32_t mn[3] = {hb[0], hb[1], hb[2]}, mx[3] = {hb[3], hb[4], hb[5]};
     int64_t ext = 0;
-    for (int a = 0; a < 3; a++) {
-        int64_t e = (int64_t)mx[a] - mn[a];
-        if (e >= (1 << 21)) return PDD_ERANGE;
-        if (e > ext) ext = e;
-    }
+    int64_t ext_axis[3] = {0, 0, 0};
+    for (int sg = 0; sg < nseg; sg++)
+        for (int a = 0; a < 3; a++) {
+            const int64_t e = (int64_t)hb[6 * sg + 3 + a] - hb[6 * sg + a];
+            if (e >= (1 << 21)) return PDD_ERANGE;
+            if (e > ext) ext = e;
+            if (e > ext_axis[a]) ext_axis[a] = e;
+        }
     int bits_axis = 0;
     while (bits_axis < 21 && ((int64_t)1 << bits_axis) <= ext) bits_axis++;
     if (bits_axis == 0) bits_axis = 1;
+    int seg_bits = 0;
+    while ((1ll << seg_bits) < nseg) seg_bits++;
+    if (3 * bits_axis + seg_bits > 63) return PDD_ERANGE;
 
-    hipLaunchKernelGGL(morton_k, dim3(grid_for(n)), dim3(kBlock), 0, c->stream, xyz, n, sw, mn[0], mn[1], mn[2],
+    hipLaunchKernelGGL(morton_k, dim3(grid_for(n)), dim3(kBlock), 0, c->stream, xyz, n, sw, doff, nseg, bnd, bits_axis,
                        keys, vals);
     PDD_HIP(c, hipGetLastError());
     uint64_t* sk;
     uint32_t* sv;
-    int rc = radix_sort_pairs(c, keys, vals, n, 3 * bits_axis, &sk, &sv);
+    int rc = radix_sort_pairs(c, keys, vals, n, 3 * bits_axis + seg_bits, &sk, &sv);
     if (rc) return rc;
 
     if ((rc = alloc_dev(c, (void**)&g->pts, (size_t)n * sizeof(int4)))) return rc;
-    hipLaunchKernelGGL(permute_k, dim3(grid_for(n)), dim3(kBlock), 0, c->stream, xyz, sw, sv, n, g->pts);
+    if (nseg > 1 && (rc = alloc_dev(c, (void**)&g->seg, (size_t)n * 4))) return rc;
+    hipLaunchKernelGGL(permute_k, dim3(grid_for(n)), dim3(kBlock), 0, c->stream, xyz, sw, sk, sv, n, bits_axis, bnd,
+                       g->pts, g->seg);
     PDD_HIP(c, hipGetLastError());
 
     int s0 = voxel_log2;
-    if (s0 == 0 && (rc = choose_finest(c, sk, n, &s0))) return rc;
+    if (s0 == 0 && (rc = choose_finest(c, sk, n, bits_axis, &s0))) return rc;
+    if (s0 > bits_axis) s0 = bits_axis;
 
     GridView& v = g->v;
     v.pts = g->pts;
     v.n = n;
-    v.minx = mn[0];
-    v.miny = mn[1];
-    v.minz = mn[2];
+    v.minx = v.miny = v.minz = 0;  // points are relative to their segment's corner
+    v.seg = g->seg;
+    v.nseg = nseg;
+    v.bits_axis = bits_axis;
 
     // level 0 from the sorted point codes
     Level* l0 = &g->lev[0];
@@ -342,9 +416,10 @@ int build_grid(Ctx* c, const int32_t* xyz, int64_t n64, int stride, int voxel_lo
         Level* L = &g->lev[l];
         bool top = true;
         for (int a = 0; a < 3; a++) {
-            lv.cmax[a] = (int32_t)(((int64_t)mx[a] - mn[a]) >> sl);
+            lv.cmax[a] = (int32_t)(ext_axis[a] >> sl);
             if (lv.cmax[a] > 1) top = false;
         }
+        lv.segshift = 3 * (bits_axis - sl);
         lv.start = L->start;
         lv.hkeys = L->hkeys;
         lv.hvals = L->hvals;
@@ -354,7 +429,7 @@ int build_grid(Ctx* c, const int32_t* xyz, int64_t n64, int stride, int voxel_lo
         lv.ncells = L->ncells;
         lv.s = sl;
         lv.parent = nullptr;
-        if ((top && nlev >= 2) || sl == 21 || nlev == kMaxLevels) break;
+        if ((top && nlev >= 2) || sl >= bits_axis || nlev == kMaxLevels) break;
         // level l + 1
         Level* U = &g->lev[l + 1];
         const uint32_t nc = L->ncells;

@@ -120,12 +120,14 @@ __global__ void __launch_bounds__(kBlock) pr_feat_k(GridView g, const uint32_t* 
         const int L = level_of_gid(g, gid);
         const LevelView& lv = g.lv[L];
         const uint64_t code = lv.key[gid - lv.base];
-        const int cx = (int)compact21(code), cy = (int)compact21(code >> 1), cz = (int)compact21(code >> 2);
+        const uint32_t sg = (uint32_t)(code >> lv.segshift);
+        const uint64_t mc = code & ((1ull << lv.segshift) - 1ull);
+        const int cx = (int)compact21(mc), cy = (int)compact21(mc >> 1), cz = (int)compact21(mc >> 2);
         const LevelView& ls = g.lv[L - 1];
         const int x = 2 * cx + (lane & 3) - 1, y = 2 * cy + ((lane >> 2) & 3) - 1, z = 2 * cz + (lane >> 4) - 1;
         uint32_t cnt = 0;
         if (x >= 0 && y >= 0 && z >= 0 && x <= ls.cmax[0] && y <= ls.cmax[1] && z <= ls.cmax[2]) {
-            const uint32_t c = hash_find(ls.hkeys, ls.hvals, ls.hmask, morton3((uint32_t)x, (uint32_t)y, (uint32_t)z));
+            const uint32_t c = hash_find(ls.hkeys, ls.hvals, ls.hmask, cell_code(ls, sg, x, y, z));
             if (c != kNone) cnt = ls.start[c + 1] - ls.start[c];
         }
         feat[(size_t)t * kF + lane] = to_bf16(log1pf((float)cnt));

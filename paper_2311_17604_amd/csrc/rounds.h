@@ -18,9 +18,8 @@ struct RoundDev {
     uint32_t pool_count, pool_cap, overflow;
     uint32_t stat_research, stat_danger, stat_touch, stat_surv;
     uint32_t lev_t[kLev];         // level(x) = #{j >= 1 : bin0(cost x) >= lev_t[j]}
-    uint64_t glob_block[kLev];    // survivors of level j with cost < this wait
-    uint64_t top_cost;            // the round's highest key (never waits)
-    int32_t top_orig, pad2;
+    uint32_t nOvf;                // A points of segments whose A exceeds their budget
+    uint32_t nA2;                 // A after the per-segment budget cut
     float frac;                   // share of alive points ranked this round (adapted)
     float frac_max;
     uint32_t work;                // survivors enumerated by the danger checks, this round
@@ -63,6 +62,14 @@ struct RoundArrays {
     const uint32_t* grp_lo; // [n] run of points with identical coordinates around each
     const uint32_t* grp_hi; //     point in Morton order: [grp_lo, grp_hi)
     uint32_t* gsafe;        // [n] round stamp: at least k alive identical points rank below
+    // segments (independent clouds of one batch; one segment otherwise)
+    const uint32_t* seg;    // [n] segment of each point (nullptr: one segment)
+    uint32_t* seg_left;     // [nseg] removals still to do
+    uint32_t* seg_cntA;     // [nseg] A points, this round
+    uint64_t* seg_glob;     // [nseg * kLev] survivors of level j with cost below this wait, this round
+    uint64_t* seg_top_cost; // [nseg] highest key of the segment's A (never waits), this round
+    int32_t* seg_top_orig;  // [nseg]
+    uint32_t* ovf;          // [n] A points of over-budget segments
     uint32_t* cS;           // [ncells0 + 1] survivors per level-0 cell, this round
     uint32_t* surv_off;     // [ncells0 + 1] exclusive scan of cS
     uint32_t* surv_bucket;  // [n] survivors grouped by level-0 cell, in cell order
@@ -71,7 +78,10 @@ struct RoundArrays {
     float frac;
     int check;
     uint32_t ncells0;
+    int nseg;
 };
+
+__device__ inline uint32_t seg_of_pt(const RoundArrays& a, uint32_t x) { return a.seg ? a.seg[x] : 0u; }
 
 __device__ inline uint32_t wave_append(uint32_t* counter, bool pred) {
     const uint64_t m = __ballot(pred);

@@ -35,6 +35,7 @@
 #include <stdio.h>
 
 #include <type_traits>
+#include <vector>
 
 #include "rounds.h"
 
@@ -76,8 +77,7 @@ __global__ void rb_begin(RoundArrays a) {
                 st->round++;
                 st->nA = st->nCand = st->nDanger = st->nSurv = st->nTouch = st->nResearch = st->nR = 0;
                 st->mode = 0;
-                st->top_cost = 0;
-                st->top_orig = 0x7FFFFFFF;
+                st->nOvf = 0;
                 st->work = 0;
                 for (int j = 0; j < kLev; j++) st->surv_min[j] = ~0ull;
             }
@@ -96,8 +96,11 @@ __global__ void __launch_bounds__(kBlock) rb_hist0(RoundArrays a, int par) {
     __syncthreads();
     const uint32_t na = st->n_alive;
     const uint32_t* L = a.alive_list[par];
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < na; t += gridDim.x * blockDim.x)
-        atomicAdd(&h[bin0(a.cost[L[t]])], 1u);
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < na; t += gridDim.x * blockDim.x) {
+        const uint32_t x = L[t];
+        if (a.seg && a.seg_left[a.seg[x]] == 0) continue;  // segment done: not ranked
+        atomicAdd(&h[bin0(a.cost[x])], 1u);
+    }
     __syncthreads();
     for (int i = threadIdx.x; i < kSelBins0; i += blockDim.x)
         if (h[i]) atomicAdd(&a.hist[i], h[i]);
@@ -144,7 +147,16 @@ __device__ void find_bin(const uint32_t* hist, int nbins, uint32_t need, uint32_
 __global__ void __launch_bounds__(kBlock) rb_find0(RoundArrays a) {
     RoundDev* st = a.st;
     if (st->done || st->err) return;
-    __shared__ uint32_t b, need;
+    __shared__ uint32_t b, need, total;
+    // the m of this round, at most the ranked (eligible) points
+    if (threadIdx.x == 0) total = 0;
+    __syncthreads();
+    uint32_t part = 0;
+    for (int i = threadIdx.x; i < kSelBins0; i += blockDim.x) part += a.hist[i];
+    atomicAdd(&total, part);
+    __syncthreads();
+    if (threadIdx.x == 0 && total < st->m) st->m = total > 0 ? total : 1u;
+    __syncthreads();
     find_bin(a.hist, kSelBins0, st->m, &b, &need);
     if (threadIdx.x == 0) {
         st->sel_bin = b;
@@ -160,7 +172,6 @@ __global__ void __launch_bounds__(kBlock) rb_find0(RoundArrays a) {
         // (the part taken from bin b is in level 0)
         st->lev_t[0] = 0;
         for (int j = 1; j < kLev; j++) st->lev_t[j] = 0xFFFFFFFFu;
-        for (int j = 0; j < kLev; j++) st->glob_block[j] = 0;
         const uint64_t total = mode == 0 ? above : st->m;
         uint64_t cum = mode == 0 ? 0 : need;
         int j = 1;
@@ -193,12 +204,13 @@ __global__ void __launch_bounds__(kBlock) rb_collect0(RoundArrays a, int par) {
             item[e] = 0;
             if (t < na) {
                 const uint32_t i = L[t];
-                const uint32_t bb = bin0(a.cost[i]);
+                const bool elig = !(a.seg && a.seg_left[a.seg[i]] == 0);  // segment done: not ranked
+                const uint32_t bb = elig ? bin0(a.cost[i]) : 0u;
                 item[e] = i;
-                if (bb > bsel) {
+                if (elig && bb > bsel) {
                     selA |= 1u << e;
                     nA++;
-                } else if (mode == 1 && bb == bsel) {
+                } else if (elig && mode == 1 && bb == bsel) {
                     selC |= 1u << e;
                     nC++;
                 }
@@ -312,6 +324,108 @@ __global__ void __launch_bounds__(1024) rb_refine(RoundArrays a) {
 }
 
 // ---------------------------------------------------------------------------
+// per-segment budgets (a batch of independent clouds)
+// ---------------------------------------------------------------------------
+
+// this round's per-segment counters and bounds back to their start values
+__global__ void __launch_bounds__(kBlock) rb_seg_reset(RoundArrays a) {
+    if (a.st->done || a.st->err) return;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < a.nseg; s += gridDim.x * blockDim.x) {
+        a.seg_cntA[s] = 0;
+        a.seg_top_cost[s] = 0;
+        a.seg_top_orig[s] = 0x7FFFFFFF;
+#pragma unroll
+        for (int j = 0; j < kLev; j++) a.seg_glob[(size_t)s * kLev + j] = 0;
+    }
+}
+
+// A points per segment, then the A points of the segments whose A holds
+// more than their remaining budget (those keep only their top keys)
+__global__ void __launch_bounds__(kBlock) rb_seg_count(RoundArrays a) {
+    RoundDev* st = a.st;
+    if (st->done || st->err) return;
+    const uint32_t nA = st->nA;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nA; t += gridDim.x * blockDim.x)
+        atomicAdd(&a.seg_cntA[a.seg[a.A[t]]], 1u);
+}
+
+__global__ void __launch_bounds__(kBlock) rb_seg_over(RoundArrays a) {
+    RoundDev* st = a.st;
+    if (st->done || st->err) return;
+    const uint32_t nA = st->nA;
+    const uint32_t n_it = (nA + blockDim.x - 1) / blockDim.x * blockDim.x;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_it; t += gridDim.x * blockDim.x) {
+        uint32_t x = 0;
+        bool over = false;
+        if (t < nA) {
+            x = a.A[t];
+            const uint32_t sx = a.seg[x];
+            over = a.seg_cntA[sx] > a.seg_left[sx];
+        }
+        const uint32_t p = wave_append(&st->nOvf, over);
+        if (over) a.ovf[p] = x;
+    }
+}
+
+// sort keys of the over-budget A points: original index, then the
+// complement of the cost, then the segment (three stable passes give
+// segment ascending, key descending)
+__global__ void __launch_bounds__(kBlock) ovf_keys_k(RoundArrays a, int pass, const uint32_t* __restrict__ src,
+                                                     uint32_t m, uint64_t* __restrict__ keys,
+                                                     uint32_t* __restrict__ vals) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
+        const uint32_t x = src[t];
+        keys[t] = pass == 0 ? (uint64_t)(uint32_t)a.pts[x].w : (pass == 1 ? ~a.cost[x] : (uint64_t)a.seg[x]);
+        vals[t] = x;
+    }
+}
+
+// first sorted position of each segment, then drop the points ranked at or
+// beyond their segment's budget from A
+__global__ void __launch_bounds__(kBlock) ovf_first_k(RoundArrays a, const uint32_t* __restrict__ sorted, uint32_t m,
+                                                      uint32_t* __restrict__ first) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
+        const uint32_t sx = a.seg[sorted[t]];
+        if (t == 0 || a.seg[sorted[t - 1]] != sx) first[sx] = t;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) ovf_drop_k(RoundArrays a, const uint32_t* __restrict__ sorted, uint32_t m,
+                                                     const uint32_t* __restrict__ first) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
+        const uint32_t x = sorted[t], sx = a.seg[x];
+        if (t - first[sx] >= a.seg_left[sx]) a.inA[x] = 0;
+    }
+}
+
+// A without the dropped points (into cand[1], then back)
+__global__ void __launch_bounds__(kBlock) ovf_compact_k(RoundArrays a) {
+    RoundDev* st = a.st;
+    const uint32_t nA = st->nA, round = st->round;
+    const uint32_t n_it = (nA + blockDim.x - 1) / blockDim.x * blockDim.x;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_it; t += gridDim.x * blockDim.x) {
+        uint32_t x = 0;
+        bool keep = false;
+        if (t < nA) {
+            x = a.A[t];
+            keep = a.inA[x] == round;
+        }
+        const uint32_t p = wave_append(&st->nA2, keep);
+        if (keep) a.cand[1][p] = x;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) ovf_copy_k(RoundArrays a) {
+    RoundDev* st = a.st;
+    const uint32_t m = st->nA2;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) a.A[t] = a.cand[1][t];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->nA = m;
+        st->nA2 = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // removal and re-costing
 // ---------------------------------------------------------------------------
 
@@ -333,8 +447,9 @@ __global__ void __launch_bounds__(kBlock) rb_remove(RoundArrays a, GridView g) {
                 // survivor of the level at or below its cost wait (except the
                 // round's highest key, which no point can precede)
                 const uint64_t cx = a.cost[x];
-                const bool top = cx == st->top_cost && a.pts[x].w == st->top_orig;
-                rm = top || cx >= st->glob_block[level_of(st, cx)];
+                const uint32_t sx = seg_of_pt(a, x);
+                const bool top = cx == a.seg_top_cost[sx] && a.pts[x].w == a.seg_top_orig[sx];
+                rm = top || cx >= a.seg_glob[sx * kLev + level_of(st, cx)];
             }
             // clear this round's A counts of x's cells at every level
             uint32_t c = a.of0[x];
@@ -351,6 +466,7 @@ __global__ void __launch_bounds__(kBlock) rb_remove(RoundArrays a, GridView g) {
             a.ev_cost[st->removed + p] = a.cost[x];
             a.ev_orig[st->removed + p] = a.pts[x].w;
             a.alive[x] = 0;
+            atomicSub(&a.seg_left[seg_of_pt(a, x)], 1u);
             uint32_t c = a.of0[x];
             for (int L = 0; L < g.nlev; L++) {
                 atomicSub(&a.cell_alive[g.lv[L].base + c], 1u);
@@ -573,18 +689,19 @@ __global__ void __launch_bounds__(kBlock) av_start_k(const uint32_t* __restrict_
 
 // Runs of identical coordinates (equal Morton codes, hence adjacent in the
 // sorted order): the first point of a run writes the run to all its points.
-__global__ void __launch_bounds__(kBlock) grp_init_k(const int4* __restrict__ pts, uint32_t n,
-                                                     uint32_t* __restrict__ lo, uint32_t* __restrict__ hi) {
+__global__ void __launch_bounds__(kBlock) grp_init_k(const int4* __restrict__ pts, const uint32_t* __restrict__ seg,
+                                                     uint32_t n, uint32_t* __restrict__ lo, uint32_t* __restrict__ hi) {
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
         const int4 p = pts[j];
+        const uint32_t sj = seg ? seg[j] : 0u;
         if (j > 0) {
             const int4 q = pts[j - 1];
-            if (q.x == p.x && q.y == p.y && q.z == p.z) continue;
+            if (q.x == p.x && q.y == p.y && q.z == p.z && (seg ? seg[j - 1] : 0u) == sj) continue;
         }
         uint32_t e = j + 1;
         while (e < n) {
             const int4 q = pts[e];
-            if (q.x != p.x || q.y != p.y || q.z != p.z) break;
+            if (q.x != p.x || q.y != p.y || q.z != p.z || (seg ? seg[e] : 0u) != sj) break;
             e++;
         }
         for (uint32_t i = j; i < e; i++) {
@@ -639,6 +756,47 @@ __global__ void __launch_bounds__(kBlock) ev_out_k(const uint64_t* __restrict__ 
     }
 }
 
+// segment of original index o (device offsets, nseg + 1 entries)
+__device__ inline uint32_t seg_of_orig(const int64_t* __restrict__ off, int nseg, uint32_t o) {
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int m = (lo + hi + 1) >> 1;
+        if ((uint64_t)off[m] <= o) lo = m; else hi = m - 1;
+    }
+    return (uint32_t)lo;
+}
+
+// kept indices from global to per-cloud (the global order is already
+// cloud-major because the clouds are contiguous in the input)
+__global__ void __launch_bounds__(kBlock) kept_local_k(int32_t* __restrict__ kept, uint32_t m,
+                                                       const int64_t* __restrict__ off, int nseg) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
+        const uint32_t o = (uint32_t)kept[t];
+        kept[t] = (int32_t)(o - (uint32_t)off[seg_of_orig(off, nseg, o)]);
+    }
+}
+
+// third pass of the removal order of a batch: by cloud (stable)
+__global__ void __launch_bounds__(kBlock) ev_keys3_k(const uint32_t* __restrict__ v2, uint32_t m,
+                                                     const int64_t* __restrict__ off, int nseg,
+                                                     uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
+        keys[t] = seg_of_orig(off, nseg, v2[t]);
+        vals[t] = t;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) ev_out3_k(const uint64_t* __restrict__ k2, const uint32_t* __restrict__ v2,
+                                                    const uint32_t* __restrict__ v3, uint32_t m,
+                                                    const int64_t* __restrict__ off, int nseg,
+                                                    int32_t* __restrict__ order, uint64_t* __restrict__ order_cost) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
+        const uint32_t i = v3[t], o = v2[i];
+        if (order) order[t] = (int32_t)(o - (uint32_t)off[seg_of_orig(off, nseg, o)]);
+        if (order_cost) order_cost[t] = ~k2[i];
+    }
+}
+
 inline unsigned gfor(size_t count, unsigned maxg = 4096) {
     size_t g = (count + kBlock - 1) / kBlock;
     if (g < 1) g = 1;
@@ -653,10 +811,11 @@ enum {
     kSTouch, kSResearch, kSR, kSEvC, kSEvO, kSHist, kSRevOff, kSRevSrc, kSHead, kSPoolS, kSPoolN, kSSt, kSTmp,
     kSFin1, kSFin2, kSSurv,
     kSCellAlive = 60, kSCellA, kSDgC, kSDgO, kSDgD, kSSurvOff, kSSurvList, kSSurvBucket, kSCS, kSGrpLo, kSGrpHi,
-    kSGSafe, kSAPts, kSAStart, kSAFlag, kSAPos
+    kSGSafe, kSAPts, kSAStart, kSAFlag, kSAPos,
+    kSOvfK0 = 89, kSOvfV0, kSOvfK1, kSOvfV1, kSSegFirst, kSSeg, kSOff, kSSegCnt, kSSegGlob, kSSegTopC, kSSegTopO
 };
 static_assert(kSSurv < 40, "scratch slots overlap the scan's");
-static_assert(kSAPos < 96, "scratch slots beyond the context's table");
+static_assert(kSAPos < 76 && kSSegTopO < kScratchSlots, "scratch slots beyond the context's table");
 
 int build_reverse(Ctx* c, RoundArrays& a, uint32_t n) {
     uint32_t* deg = (uint32_t*)scratch(c, kSTmp, (size_t)(n + 1) * 4);
@@ -701,16 +860,60 @@ int build_alive_view(Ctx* c, const RoundArrays& a, const GridView& g, GridView* 
     return PDD_OK;
 }
 
+// A batch: keep, in each segment whose A exceeds its remaining budget B_s,
+// only its top B_s keys (A stays an upper set of every segment's keys).
+// Reads the count of such A points back to size the sort.
+int segment_budgets(Ctx* c, RoundArrays& a) {
+    hipLaunchKernelGGL(rb_seg_count, dim3(1024), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(rb_seg_over, dim3(1024), dim3(kBlock), 0, c->stream, a);
+    PDD_HIP(c, hipGetLastError());
+    uint32_t* h = (uint32_t*)((char*)c->pinned + 2048);
+    PDD_HIP(c, hipMemcpyAsync(h, &a.st->nOvf, 4, hipMemcpyDeviceToHost, c->stream));
+    PDD_HIP(c, hipStreamSynchronize(c->stream));
+    const uint32_t m = h[0];
+    if (m == 0) return PDD_OK;
+    uint64_t* k0 = (uint64_t*)scratch(c, kSOvfK0, (size_t)m * 8);
+    uint32_t* v0 = (uint32_t*)scratch(c, kSOvfV0, (size_t)m * 4);
+    uint64_t* k1 = (uint64_t*)scratch(c, kSOvfK1, (size_t)m * 8);
+    uint32_t* v1 = (uint32_t*)scratch(c, kSOvfV1, (size_t)m * 4);
+    uint32_t* first = (uint32_t*)scratch(c, kSSegFirst, (size_t)a.nseg * 4);
+    if (!k0 || !v0 || !k1 || !v1 || !first) return PDD_ENOMEM;
+    int seg_bits = 1;
+    while ((1ll << seg_bits) < a.nseg) seg_bits++;
+    const int passes[3] = {31, 64, seg_bits};
+    const uint32_t* src = a.ovf;
+    uint64_t* sk;
+    uint32_t* sv = nullptr;
+    for (int p = 0; p < 3; p++) {
+        uint64_t* kk = (p & 1) ? k1 : k0;
+        uint32_t* vv = (p & 1) ? v1 : v0;
+        hipLaunchKernelGGL(ovf_keys_k, dim3(gfor(m)), dim3(kBlock), 0, c->stream, a, p, src, m, kk, vv);
+        PDD_HIP(c, hipGetLastError());
+        int rc = radix_sort_pairs(c, kk, vv, m, passes[p], &sk, &sv);
+        if (rc) return rc;
+        src = sv;
+    }
+    hipLaunchKernelGGL(ovf_first_k, dim3(gfor(m)), dim3(kBlock), 0, c->stream, a, sv, m, first);
+    hipLaunchKernelGGL(ovf_drop_k, dim3(gfor(m)), dim3(kBlock), 0, c->stream, a, sv, m, first);
+    hipLaunchKernelGGL(ovf_compact_k, dim3(1024), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(ovf_copy_k, dim3(1024), dim3(kBlock), 0, c->stream, a);
+    PDD_HIP(c, hipGetLastError());
+    return PDD_OK;
+}
+
 template <int K>
 int launch_round(Ctx* c, RoundArrays& a, const GridView& g, const GridView& gs, int par) {
     const unsigned G = 1024;
     hipLaunchKernelGGL(rb_begin, dim3(1), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(rb_seg_reset, dim3(gfor(a.nseg)), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_hist0, dim3(G), dim3(kBlock), 0, c->stream, a, par);
     hipLaunchKernelGGL(rb_find0, dim3(1), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_collect0, dim3(G), dim3(kBlock), 0, c->stream, a, par);
     hipLaunchKernelGGL(rb_refine, dim3(1), dim3(1024), 0, c->stream, a);
     PDD_HIP(c, hipGetLastError());
-    int rc = launch_blocking(c, a, g, K);
+    int rc;
+    if (a.nseg > 1 && (rc = segment_budgets(c, a))) return rc;
+    rc = launch_blocking(c, a, g, K);
     if (rc) return rc;
     hipLaunchKernelGGL(rb_remove, dim3(G), dim3(kBlock), 0, c->stream, a, g);
     hipLaunchKernelGGL(rb_remove_end, dim3(1), dim3(1), 0, c->stream, a);
@@ -773,10 +976,16 @@ int run_rounds(Ctx* c, RoundArrays& a, const GridView& g, uint32_t n) {
 
 }  // namespace
 
-int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, int64_t keep, int32_t* kept,
-             int32_t* order, uint64_t* order_cost) {
+int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, const int64_t* h_off,
+             const int64_t* h_keep, int nseg, int32_t* kept, int32_t* order, uint64_t* order_cost) {
     const GridView& g = grid.v;
     const uint32_t n = g.n;
+    int64_t keep = 0;
+    std::vector<uint32_t> left((size_t)nseg);
+    for (int s = 0; s < nseg; s++) {
+        keep += h_keep[s];
+        left[s] = (uint32_t)(h_off[s + 1] - h_off[s] - h_keep[s]);
+    }
     const uint32_t target = (uint32_t)(n - keep);
     RoundArrays a{};
     a.pts = g.pts;
@@ -833,6 +1042,14 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, int6
     a.grp_hi = ghi;
     ALLOC(gsafe, kSGSafe, (size_t)n * 4);
     a.ncells0 = ncells0;
+    a.nseg = nseg;
+    a.seg = g.seg;
+    ALLOC(seg_left, kSSeg, (size_t)nseg * 4);
+    ALLOC(seg_cntA, kSSegCnt, (size_t)nseg * 4);
+    ALLOC(seg_glob, kSSegGlob, (size_t)nseg * kLev * 8);
+    ALLOC(seg_top_cost, kSSegTopC, (size_t)nseg * 8);
+    ALLOC(seg_top_orig, kSSegTopO, (size_t)nseg * 4);
+    a.ovf = a.R;  // the removal list is free while A is selected
     ALLOC(st, kSSt, sizeof(RoundDev));
 #undef ALLOC
     int rc;
@@ -844,7 +1061,11 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, int6
     if ((rc = fill_u32(c, a.cellAlev, 0, (size_t)tcells * kLev))) return rc;
     if ((rc = fill_u32(c, a.cS, 0, ncells0 + 1))) return rc;
     if ((rc = fill_u32(c, a.gsafe, 0, n))) return rc;
-    hipLaunchKernelGGL(grp_init_k, dim3(gfor(n)), dim3(kBlock), 0, c->stream, g.pts, n, glo, ghi);
+    PDD_HIP(c, hipMemcpyAsync(a.seg_left, left.data(), (size_t)nseg * 4, hipMemcpyHostToDevice, c->stream));
+    int64_t* doff = (int64_t*)scratch(c, kSOff, (size_t)(nseg + 1) * 8);
+    if (!doff) return PDD_ENOMEM;
+    PDD_HIP(c, hipMemcpyAsync(doff, h_off, (size_t)(nseg + 1) * 8, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(grp_init_k, dim3(gfor(n)), dim3(kBlock), 0, c->stream, g.pts, g.seg, n, glo, ghi);
     if ((rc = iota_u32(c, a.alive_list[0], n))) return rc;
     for (int L = 0; L < g.nlev; L++)
         hipLaunchKernelGGL(cell_count_k, dim3(gfor(g.lv[L].ncells)), dim3(kBlock), 0, c->stream, g.lv[L].start,
@@ -878,6 +1099,8 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, int6
     PDD_HIP(c, hipGetLastError());
     if ((rc = exclusive_scan_u32(c, flag_o, pos, n, nullptr))) return rc;
     hipLaunchKernelGGL(kept_write_k, dim3(gfor(n)), dim3(kBlock), 0, c->stream, flag_o, pos, n, (uint32_t)keep, kept);
+    if (nseg > 1)
+        hipLaunchKernelGGL(kept_local_k, dim3(gfor(keep)), dim3(kBlock), 0, c->stream, kept, (uint32_t)keep, doff, nseg);
     PDD_HIP(c, hipGetLastError());
 
     // order: removals sorted by (cost desc, original index asc)
@@ -898,8 +1121,29 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, int6
                            keys2, vals2);
         PDD_HIP(c, hipGetLastError());
         if ((rc = radix_sort_pairs(c, keys2, vals2, target, 64, &sk, &sv))) return rc;
-        hipLaunchKernelGGL(ev_out_k, dim3(gfor(target)), dim3(kBlock), 0, c->stream, sk, sv, target, order,
-                           order_cost);
+        if (nseg == 1) {
+            hipLaunchKernelGGL(ev_out_k, dim3(gfor(target)), dim3(kBlock), 0, c->stream, sk, sv, target, order,
+                               order_cost);
+        } else {
+            // cloud-major: a stable third pass by cloud, indices made per-cloud
+            uint64_t* k3 = (uint64_t*)scratch(c, kSOvfK0, (size_t)target * 8);
+            uint32_t* v3 = (uint32_t*)scratch(c, kSOvfV0, (size_t)target * 4);
+            uint64_t* k2s = (uint64_t*)scratch(c, kSOvfK1, (size_t)target * 8);
+            uint32_t* v2s = (uint32_t*)scratch(c, kSOvfV1, (size_t)target * 4);
+            if (!k3 || !v3 || !k2s || !v2s) return PDD_ENOMEM;
+            PDD_HIP(c, hipMemcpyAsync(k2s, sk, (size_t)target * 8, hipMemcpyDeviceToDevice, c->stream));
+            PDD_HIP(c, hipMemcpyAsync(v2s, sv, (size_t)target * 4, hipMemcpyDeviceToDevice, c->stream));
+            hipLaunchKernelGGL(ev_keys3_k, dim3(gfor(target)), dim3(kBlock), 0, c->stream, v2s, target, doff, nseg, k3,
+                               v3);
+            PDD_HIP(c, hipGetLastError());
+            int sbits = 1;
+            while ((1ll << sbits) < nseg) sbits++;
+            uint64_t* sk3;
+            uint32_t* sv3;
+            if ((rc = radix_sort_pairs(c, k3, v3, target, sbits, &sk3, &sv3))) return rc;
+            hipLaunchKernelGGL(ev_out3_k, dim3(gfor(target)), dim3(kBlock), 0, c->stream, k2s, v2s, sv3, target, doff,
+                               nseg, order, order_cost);
+        }
         PDD_HIP(c, hipGetLastError());
     }
     mark(c, kPhFinal);

@@ -180,6 +180,7 @@ __device__ void wave_knn(const GridView& g, uint32_t q, int4 qp, const SearchCtx
                          uint32_t* tested = nullptr) {
     const int lane = (int)lane_id();
     const int ux = qp.x - g.minx, uy = qp.y - g.miny, uz = qp.z - g.minz;
+    const uint32_t qs = seg_at(g, q);
     my_d = ~0ull;
     my_id = -1;
     uint64_t cert = 0;  // squared radius around the query within which every point was tested
@@ -205,8 +206,7 @@ __device__ void wave_knn(const GridView& g, uint32_t q, int4 qp, const SearchCtx
                     const int x = cx + dx, y = cy + dy, z = cz + dz;
                     if (m == r && x >= 0 && y >= 0 && z >= 0 && x <= lv.cmax[0] && y <= lv.cmax[1] &&
                         z <= lv.cmax[2]) {
-                        const uint32_t c =
-                            hash_find(lv.hkeys, lv.hvals, lv.hmask, morton3((uint32_t)x, (uint32_t)y, (uint32_t)z));
+                        const uint32_t c = hash_find(lv.hkeys, lv.hvals, lv.hmask, cell_code(lv, qs, x, y, z));
                         if (c != kNone) {
                             st = lv.start[c];
                             cnt = lv.start[c + 1] - st;
@@ -247,6 +247,7 @@ __device__ bool wave_knn_ball(const GridView& g, uint32_t q, int4 qp, const Sear
                               uint32_t* tested = nullptr) {
     const int lane = (int)lane_id();
     const int ux = qp.x - g.minx, uy = qp.y - g.miny, uz = qp.z - g.minz;
+    const uint32_t qs = seg_at(g, q);
     my_d = ~0ull;
     my_id = -1;
     const int ri = (int)sqrt((double)r2) + 1;
@@ -266,8 +267,7 @@ __device__ bool wave_knn_ball(const GridView& g, uint32_t q, int4 qp, const Sear
             const int x = x0 + idx % nx, y = y0 + (idx / nx) % ny, z = z0 + idx / (nx * ny);
             const uint64_t gx = cell_gap(ux, x, s), gy = cell_gap(uy, y, s), gz = cell_gap(uz, z, s);
             if (gx * gx + gy * gy + gz * gz <= r2) {
-                const uint32_t c =
-                    hash_find(lv.hkeys, lv.hvals, lv.hmask, morton3((uint32_t)x, (uint32_t)y, (uint32_t)z));
+                const uint32_t c = hash_find(lv.hkeys, lv.hvals, lv.hmask, cell_code(lv, qs, x, y, z));
                 if (c != kNone) {
                     st = lv.start[c];
                     cnt = lv.start[c + 1] - st;

@@ -60,6 +60,8 @@ def load():
     lib.pdd_knn_cost.restype = ctypes.c_int
     lib.pdd_decimate.argtypes = [P, P, i64, i64, ctypes.POINTER(Opts), P, P, P]
     lib.pdd_decimate.restype = ctypes.c_int
+    lib.pdd_decimate_batch.argtypes = [P, P, P, i32, P, ctypes.POINTER(Opts), P, P, P]
+    lib.pdd_decimate_batch.restype = ctypes.c_int
     lib.pdd_last_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.c_int]
     lib.pdd_last_stats.restype = ctypes.c_int
     lib.pdd_last_timing.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
@@ -189,6 +191,35 @@ def decimate(ctx: Context, xyz, keep: int, k: int, b: int = 0, voxel_log2: int =
              | (PDD_F_PROGRESS if progress else 0))
     ctx._check(ctx.lib.pdd_decimate(ctx.h, _ptr(pts), n, keep, ctypes.byref(o), _ptr(kept), _ptr(order),
                                     _ptr(order_cost)), "pdd_decimate")
+    return kept, order, order_cost
+
+
+def decimate_batch(ctx: Context, xyz, offsets, keeps, k: int, b: int = 0, voxel_log2: int = 0,
+                   round_frac: float = 0.0, check: bool = False, with_order: bool = True, timing: bool = False,
+                   progress: bool = False):
+    """Independent clouds decimated together: cloud s is rows
+    offsets[s]:offsets[s+1] of xyz and keeps keeps[s] points.  Returns
+    (kept, order, order_cost), each the clouds' results one after another,
+    indices relative to each cloud's first row."""
+    import numpy as np
+    import torch
+    pts, stride = _points(xyz)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    kp = np.ascontiguousarray(keeps, dtype=np.int64)
+    nscan = len(kp)
+    if off.shape != (nscan + 1,) or off[-1] != pts.shape[0]:
+        raise ValueError("offsets must have len(keeps) + 1 entries ending at the number of points")
+    total_keep = int(kp.sum())
+    m = int(pts.shape[0] - total_keep)
+    kept = torch.empty(total_keep, dtype=torch.int32, device=pts.device)
+    order = torch.empty(m, dtype=torch.int32, device=pts.device) if with_order else None
+    order_cost = torch.empty(m, dtype=torch.int64, device=pts.device) if with_order else None
+    o = Opts(k=k, b=b, voxel_log2=voxel_log2, round_frac=round_frac, point_stride=stride,
+             flags=(PDD_F_CHECK if check else 0) | (PDD_F_TIMING if timing else 0)
+             | (PDD_F_PROGRESS if progress else 0))
+    ctx._check(ctx.lib.pdd_decimate_batch(ctx.h, _ptr(pts), off.ctypes.data_as(ctypes.c_void_p), nscan,
+                                          kp.ctypes.data_as(ctypes.c_void_p), ctypes.byref(o), _ptr(kept),
+                                          _ptr(order), _ptr(order_cost)), "pdd_decimate_batch")
     return kept, order, order_cost
 
 
