@@ -110,19 +110,26 @@ def main():
     n = w.xyz.shape[0]
     x = torch.from_numpy(w.xyz).cuda()
     ctx = pdd.Context(0)
-    kept = torch.empty(w.keep, dtype=torch.int32, device="cuda")
-    order = torch.empty(n - w.keep, dtype=torch.int32, device="cuda")
-    oc = torch.empty(n - w.keep, dtype=torch.int64, device="cuda")
-    kw = dict(b=args.b, voxel_log2=args.voxel_log2, round_frac=args.round_frac, out=(kept, order, oc),
-              timing=True, progress=not args.quiet)
+    batch = w.offsets is not None
+    if batch:
+        kw = dict(b=args.b, voxel_log2=args.voxel_log2, round_frac=args.round_frac, timing=True,
+                  progress=not args.quiet)
+        run = lambda: pdd.decimate_batch(ctx, x, w.offsets, w.keeps, w.k, **kw)  # noqa: E731
+    else:
+        kept = torch.empty(w.keep, dtype=torch.int32, device="cuda")
+        order = torch.empty(n - w.keep, dtype=torch.int32, device="cuda")
+        oc = torch.empty(n - w.keep, dtype=torch.int64, device="cuda")
+        kw = dict(b=args.b, voxel_log2=args.voxel_log2, round_frac=args.round_frac, out=(kept, order, oc),
+                  timing=True, progress=not args.quiet)
+        run = lambda: pdd.decimate(ctx, x, w.keep, w.k, **kw)  # noqa: E731
     for i in range(args.warmup):
-        pdd.decimate(ctx, x, w.keep, w.k, **kw)
+        run()
         print("warmup %d done" % i, file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     phases = []
     for i in range(args.steps):
-        pdd.decimate(ctx, x, w.keep, w.k, **kw)
+        run()
         phases.append(ctx.timing())
         print("step %d done %s" % (i, phases[-1]), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -161,6 +168,7 @@ def main():
         "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": workload, "n": n, "k": w.k, "keep": w.keep, "method": "plain",
+                   "clouds": int(len(w.keeps)) if batch else 1,
                    "gen_s": round(t_gen, 2), "stats": st, "phase_ms": ph},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -149,8 +149,11 @@ int pdd_decimate(pdd_ctx *ctx, const int32_t *d_xyz, int64_t n, int64_t keep_cou
  *   d_order     : [sum (size - keep)] int32 or NULL: per cloud its removed
  *                 indices (relative) in removal order, clouds in order
  *   d_order_cost: [sum (size - keep)] uint64 or NULL: cost at removal
- * Each cloud's extent must fit 2^b mm per axis and the clouds 2^c ids with
- * 3b + c <= 63 (else PDD_ERANGE).  Synchronises the stream.
+ * Clouds are taken in consecutive groups of at most 2^28 points, each
+ * group one batched decimation (so the round state fits the device).
+ * Within a group each cloud's extent must fit 2^b mm per axis and the
+ * clouds 2^c ids with 3b + c <= 63 (else PDD_ERANGE).  Synchronises the
+ * stream.
  * Errors: PDD_EINVAL, PDD_ERANGE, PDD_ENOMEM, PDD_EHIP, PDD_EINTERNAL.
  */
 int pdd_decimate_batch(pdd_ctx *ctx, const int32_t *d_xyz, const int64_t *h_offsets, int32_t nscan,

@@ -1,6 +1,7 @@
 // C ABI of libpdd: argument checks, context, scratch pool and entry points.
 #include <new>
 #include <string>
+#include <vector>
 
 #include "predictor.h"
 
@@ -162,6 +163,9 @@ int pdd_knn_cost(pdd_ctx* ctx, const pdd_grid* grid, int32_t k, int32_t b, int32
     return pdd::knn_to_original(c, g, K, k + b, ko, d_nbr, d_r2k, d_cost);
 }
 
+// largest group of clouds one batched decimation takes at once (points)
+constexpr int64_t kBatchGroup = (int64_t)1 << 28;
+
 static int decimate_common(pdd_ctx* ctx, const int32_t* d_xyz, int64_t n, const int64_t* h_off, const int64_t* h_keep,
                            int nseg, const pdd_opts* opts, int32_t* d_kept, int32_t* d_order, uint64_t* d_order_cost) {
     const int k = opts->k;
@@ -217,11 +221,35 @@ int pdd_decimate_batch(pdd_ctx* ctx, const int32_t* d_xyz, const int64_t* h_offs
     if (h_offsets[0] != 0) return PDD_EINVAL;
     for (int s = 0; s < nscan; s++) {
         const int64_t ns = h_offsets[s + 1] - h_offsets[s];
-        if (ns < 2 || h_keep[s] < 1 || h_keep[s] > ns) return PDD_EINVAL;
+        if (ns < 2 || ns >= (int64_t)0x7FFFFFFF || h_keep[s] < 1 || h_keep[s] > ns) return PDD_EINVAL;
     }
-    const int64_t n = h_offsets[nscan];
-    if (n >= (int64_t)0x7FFFFFFF) return PDD_EINVAL;
-    return decimate_common(ctx, d_xyz, n, h_offsets, h_keep, nscan, opts, d_kept, d_order, d_order_cost);
+    const int stride = opts->point_stride == 0 ? 12 : opts->point_stride;
+    if (stride != 12 && stride != 16) return PDD_EINVAL;
+    // consecutive groups of clouds of at most kBatchGroup points, each one
+    // segmented decimation; the outputs of a group go after the previous ones
+    int64_t kept_at = 0, order_at = 0;
+    int first = 0;
+    while (first < nscan) {
+        int last = first + 1;
+        while (last < nscan && h_offsets[last + 1] - h_offsets[first] <= kBatchGroup) last++;
+        const int ng = last - first;
+        std::vector<int64_t> off((size_t)ng + 1), keep((size_t)ng);
+        int64_t gkeep = 0;
+        for (int s = 0; s < ng; s++) {
+            off[s] = h_offsets[first + s] - h_offsets[first];
+            keep[s] = h_keep[first + s];
+            gkeep += keep[s];
+        }
+        off[ng] = h_offsets[last] - h_offsets[first];
+        const int32_t* xyz = (const int32_t*)((const char*)d_xyz + h_offsets[first] * stride);
+        int rc = decimate_common(ctx, xyz, off[ng], off.data(), keep.data(), ng, opts, d_kept + kept_at,
+                                 d_order ? d_order + order_at : nullptr, d_order_cost ? d_order_cost + order_at : nullptr);
+        if (rc) return rc;
+        kept_at += gkeep;
+        order_at += off[ng] - gkeep;
+        first = last;
+    }
+    return PDD_OK;
 }
 
 int pdd_last_stats(const pdd_ctx* ctx, int64_t* stats, int n) {
