@@ -2,7 +2,11 @@
 
 A step is one pdd_decimate call on device-resident synthetic input: voxel
 grid, initial k-NN costs, removal rounds and finalisation, producing the kept
-indices and the removal order.  Prints one JSON line with
+indices and the removal order (pdd_decimate_batch for the batch workload).
+Before the timed steps the autotuner picks the list width, finest cell level
+and round share by timed trials on a strided sample (not timed; reported in
+config.autotune; the settings never change the result).  Prints one JSON
+line with
 
   roofline      the k-NN cost kernel: algorithmic bytes per launch (read one
                 16-byte point, write its K-entry list, cost and count) over
@@ -36,13 +40,14 @@ def knn_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, kernel: str):
     """HBM bytes per k-NN launch from the committed counter summary, or None
-    when it is missing, for another workload, or for another kernel source."""
+    when it is missing, for another workload or kernel instance, or for
+    another kernel source."""
     if not os.path.exists(COUNTERS):
         return None
     c = json.load(open(COUNTERS))
-    if c.get("workload") != workload or c.get("source_sha") != knn_source_hash():
+    if c.get("workload") != workload or c.get("kernel") != kernel or c.get("source_sha") != knn_source_hash():
         return None
     return c.get("traffic_bytes")
 
@@ -81,6 +86,9 @@ def main():
     ap.add_argument("--round-frac", type=float, default=0.0)
     ap.add_argument("--voxel-log2", type=int, default=0)
     ap.add_argument("--b", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner (by default b, voxel and round share are chosen first by timed trials "
+                         "on a sample; not timed, reported as config.autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true", help="no per-50-round progress lines from the library")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -111,6 +119,13 @@ def main():
     x = torch.from_numpy(w.xyz).cuda()
     ctx = pdd.Context(0)
     batch = w.offsets is not None
+    tune = None
+    if not args.no_autotune and not batch:
+        t_tune = time.time()
+        tune = pdd.autotune(ctx, x, w.keep, w.k, b=args.b, voxel_log2=args.voxel_log2, round_frac=args.round_frac)
+        tune["tune_s"] = round(time.time() - t_tune, 2)
+        print("autotune: %s" % tune, file=sys.stderr, flush=True)
+        args.b, args.voxel_log2, args.round_frac = tune["b"], tune["voxel_log2"], tune["round_frac"]
     if batch:
         kw = dict(b=args.b, voxel_log2=args.voxel_log2, round_frac=args.round_frac, timing=True,
                   progress=not args.quiet)
@@ -144,9 +159,10 @@ def main():
     knn_ms = ph["knn"]
     achieved = algo / (knn_ms * 1e-3) / 1e9
     workload = w.name if args.scale == 1.0 else "%s@%g" % (w.name, args.scale)
+    kname = "knn_wave_k<%d>" % K
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(workload),
-            "kernel": "knn_wave_k<%d>" % K, "algorithmic_bytes_per_launch": algo,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(workload, kname),
+            "kernel": kname, "algorithmic_bytes_per_launch": algo,
             "bytes_per_point": bytes_per_point, "avg_launch_ms": knn_ms}
 
     cpu = None
@@ -167,8 +183,9 @@ def main():
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": workload, "n": n, "k": w.k, "keep": w.keep, "method": "plain",
-                   "clouds": int(len(w.keeps)) if batch else 1,
+        "config": {"workload": workload, "n": n, "k": w.k, "keep": w.keep,
+                   "method": "batched" if batch else ("autotuned" if tune else "plain"),
+                   "clouds": int(len(w.keeps)) if batch else 1, "autotune": tune,
                    "gen_s": round(t_gen, 2), "stats": st, "phase_ms": ph},
         "roofline": roof,
         "cpu_baseline": cpu,

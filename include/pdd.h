@@ -160,6 +160,21 @@ int pdd_decimate_batch(pdd_ctx *ctx, const int32_t *d_xyz, const int64_t *h_offs
                        const int64_t *h_keep, const pdd_opts *opts, int32_t *d_kept, int32_t *d_order,
                        uint64_t *d_order_cost);
 
+/*
+ * Autotuner: chooses voxel_log2, b and round_frac for pdd_decimate of this
+ * cloud by timing trial decimations of a strided sample (every step-th
+ * point, about `sample` points; 0 = 2M) with keep scaled alike: round share,
+ * then list width, then the finest cell level relative to the automatic one.
+ * None of them can change a decimation's result, only its time.
+ *   base    : k and point_stride used; other fields are the starting point
+ *   out     : receives base with the chosen voxel_log2, b and round_frac
+ *   best_ms : (if not NULL) the best trial's time on the sample
+ * Synchronises the stream.  Errors: PDD_EINVAL, PDD_ERANGE, PDD_ENOMEM,
+ * PDD_EHIP, PDD_EINTERNAL.
+ */
+int pdd_autotune(pdd_ctx *ctx, const int32_t *d_xyz, int64_t n, int64_t keep, const pdd_opts *base,
+                 int64_t sample, pdd_opts *out, float *best_ms);
+
 /* Counters of the last pdd_decimate on this context, written to stats[0..n),
  * n <= 12:
  *   0 rounds, 1 re-searches (buffer exhausted), 2 danger checks, 3 reverse-list

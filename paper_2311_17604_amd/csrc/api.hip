@@ -166,8 +166,22 @@ int pdd_knn_cost(pdd_ctx* ctx, const pdd_grid* grid, int32_t k, int32_t b, int32
 // largest group of clouds one batched decimation takes at once (points)
 constexpr int64_t kBatchGroup = (int64_t)1 << 28;
 
+}  // extern "C"
+
+namespace pdd {
+int decimate_entry(Ctx* c, const int32_t* d_xyz, int64_t n, const int64_t* h_off, const int64_t* h_keep, int nseg,
+                   const pdd_opts* opts, int32_t* d_kept, int32_t* d_order, uint64_t* d_order_cost);
+int autotune(Ctx* c, const int32_t* d_xyz, int64_t n, int64_t keep, const pdd_opts* base, int64_t sample,
+             pdd_opts* out, float* best_ms);
+}  // namespace pdd
+
 static int decimate_common(pdd_ctx* ctx, const int32_t* d_xyz, int64_t n, const int64_t* h_off, const int64_t* h_keep,
                            int nseg, const pdd_opts* opts, int32_t* d_kept, int32_t* d_order, uint64_t* d_order_cost) {
+    return pdd::decimate_entry(&ctx->c, d_xyz, n, h_off, h_keep, nseg, opts, d_kept, d_order, d_order_cost);
+}
+
+int pdd::decimate_entry(Ctx* c, const int32_t* d_xyz, int64_t n, const int64_t* h_off, const int64_t* h_keep, int nseg,
+                        const pdd_opts* opts, int32_t* d_kept, int32_t* d_order, uint64_t* d_order_cost) {
     const int k = opts->k;
     if (k < 1 || k > pdd::kMaxK) return PDD_EINVAL;
     int b = opts->b;
@@ -179,7 +193,6 @@ static int decimate_common(pdd_ctx* ctx, const int32_t* d_xyz, int64_t n, const 
     const int stride = opts->point_stride == 0 ? 12 : opts->point_stride;
     if (stride != 12 && stride != 16) return PDD_EINVAL;
     if (opts->voxel_log2 != 0 && (opts->voxel_log2 < 2 || opts->voxel_log2 > 20)) return PDD_EINVAL;
-    Ctx* c = &ctx->c;
     if (hipSetDevice(c->device) != hipSuccess) return PDD_EHIP;
     for (auto& s : c->stats) s = 0;
     for (auto& t : c->phase_ms) t = 0.0f;
@@ -204,6 +217,8 @@ static int decimate_common(pdd_ctx* ctx, const int32_t* d_xyz, int64_t n, const 
     pdd::free_grid(&grid);
     return rc;
 }
+
+extern "C" {
 
 int pdd_decimate(pdd_ctx* ctx, const int32_t* d_xyz, int64_t n, int64_t keep_count, const pdd_opts* opts,
                  int32_t* d_kept, int32_t* d_order, uint64_t* d_order_cost) {
@@ -264,6 +279,14 @@ int pdd_last_timing(const pdd_ctx* ctx, float* ms, int n) {
     int m = n < pdd::kPhCount - 1 ? n : pdd::kPhCount - 1;
     for (int i = 0; i < m; i++) ms[i] = ctx->c.phase_ms[i];
     return m;
+}
+
+int pdd_autotune(pdd_ctx* ctx, const int32_t* d_xyz, int64_t n, int64_t keep, const pdd_opts* base, int64_t sample,
+                 pdd_opts* out, float* best_ms) {
+    if (!ctx || !d_xyz || !base || !out || n >= (int64_t)0x7FFFFFFF) return PDD_EINVAL;
+    Ctx* c = &ctx->c;
+    if (hipSetDevice(c->device) != hipSuccess) return PDD_EHIP;
+    return pdd::autotune(c, d_xyz, n, keep, base, sample, out, best_ms);
 }
 
 // ---------------------------------------------------------------------------

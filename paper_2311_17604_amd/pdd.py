@@ -62,6 +62,9 @@ def load():
     lib.pdd_decimate.restype = ctypes.c_int
     lib.pdd_decimate_batch.argtypes = [P, P, P, i32, P, ctypes.POINTER(Opts), P, P, P]
     lib.pdd_decimate_batch.restype = ctypes.c_int
+    lib.pdd_autotune.argtypes = [P, P, i64, i64, ctypes.POINTER(Opts), i64, ctypes.POINTER(Opts),
+                                 ctypes.POINTER(ctypes.c_float)]
+    lib.pdd_autotune.restype = ctypes.c_int
     lib.pdd_last_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.c_int]
     lib.pdd_last_stats.restype = ctypes.c_int
     lib.pdd_last_timing.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
@@ -192,6 +195,21 @@ def decimate(ctx: Context, xyz, keep: int, k: int, b: int = 0, voxel_log2: int =
     ctx._check(ctx.lib.pdd_decimate(ctx.h, _ptr(pts), n, keep, ctypes.byref(o), _ptr(kept), _ptr(order),
                                     _ptr(order_cost)), "pdd_decimate")
     return kept, order, order_cost
+
+
+def autotune(ctx: Context, xyz, keep: int, k: int, sample: int = 0, b: int = 0, voxel_log2: int = 0,
+             round_frac: float = 0.0):
+    """Chosen settings for decimating xyz: dict(b, voxel_log2, round_frac,
+    best_ms) from timed trials on a strided sample (results never depend on
+    them)."""
+    pts, stride = _points(xyz)
+    base = Opts(k=k, b=b, voxel_log2=voxel_log2, round_frac=round_frac, point_stride=stride, flags=0)
+    out = Opts()
+    ms = ctypes.c_float()
+    ctx._check(ctx.lib.pdd_autotune(ctx.h, _ptr(pts), pts.shape[0], keep, ctypes.byref(base), sample,
+                                    ctypes.byref(out), ctypes.byref(ms)), "pdd_autotune")
+    return {"b": int(out.b), "voxel_log2": int(out.voxel_log2), "round_frac": float(out.round_frac),
+            "best_ms": float(ms.value)}
 
 
 def decimate_batch(ctx: Context, xyz, offsets, keeps, k: int, b: int = 0, voxel_log2: int = 0,
