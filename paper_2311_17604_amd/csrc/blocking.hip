@@ -131,20 +131,40 @@ __global__ void __launch_bounds__(kBlock) rb_survive(RoundArrays a, GridView g) 
         uint32_t x = 0;
         uint64_t cmax = 0;
         int lev = 0;
-        if (t < nA) {
+        const bool act = t < nA;
+        if (act) {
             x = a.A[t];
             cmax = a.cost[x];
             lev = level_of(st, cmax);
-            const uint32_t c0 = a.of0[x];
-            uint32_t c = c0;
-            for (int L = 0; L < g.nlev; L++) {
-                atomicAdd(&a.cellAlev[(size_t)(g.lv[L].base + c) * kLev + lev], 1u);
-                if (L + 1 < g.nlev) c = g.lv[L].parent[c];
+        }
+        // A counts of x's cells at every level; where the whole wave's A
+        // points share a cell (coarse levels: A arrives in index order, so
+        // a wave's points are neighbours) one lane adds the wave's counts
+        {
+            uint32_t c = act ? a.of0[x] : 0u;
+            const uint64_t am = __ballot(act);
+            const int leader = am ? __ffsll((unsigned long long)am) - 1 : 0;
+            for (int L = 0; L < g.nlev && am; L++) {
+                const uint32_t gc = g.lv[L].base + c;
+                const uint32_t g0 = (uint32_t)__shfl((int)gc, leader, kWave);
+                if (__all(!act || gc == g0)) {
+#pragma unroll
+                    for (int j = 0; j < kLev; j++) {
+                        const uint32_t cnt = (uint32_t)__popcll(__ballot(act && lev == j));
+                        if ((int)(threadIdx.x & (kWave - 1)) == leader && cnt)
+                            atomicAdd(&a.cellAlev[(size_t)g0 * kLev + j], cnt);
+                    }
+                } else if (act) {
+                    atomicAdd(&a.cellAlev[(size_t)gc * kLev + lev], 1u);
+                }
+                if (act && L + 1 < g.nlev) c = g.lv[L].parent[c];
             }
+        }
+        if (act) {
             if (a.blocked[x] != round && a.gsafe[x] != round) {
                 sv = true;
                 a.surv[x] = round;
-                atomicAdd(&a.cS[c0], 1u);
+                atomicAdd(&a.cS[a.of0[x]], 1u);
             }
         }
         const uint32_t p = wave_append(&st->nSurv, sv);

@@ -451,13 +451,31 @@ __global__ void __launch_bounds__(kBlock) rb_remove(RoundArrays a, GridView g) {
                 const bool top = cx == a.seg_top_cost[sx] && a.pts[x].w == a.seg_top_orig[sx];
                 rm = top || cx >= a.seg_glob[sx * kLev + level_of(st, cx)];
             }
-            // clear this round's A counts of x's cells at every level
-            uint32_t c = a.of0[x];
-            for (int L = 0; L < g.nlev; L++) {
-                const size_t gc = (size_t)(g.lv[L].base + c) * kLev;
+        }
+        // clear this round's A counts of x's cells at every level, and take
+        // the removed points off the alive counts (one lane per wave where
+        // the wave's points share the cell)
+        {
+            const bool act = t < nA;
+            uint32_t c = act ? a.of0[x] : 0u;
+            const uint64_t am = __ballot(act);
+            const int leader = am ? __ffsll((unsigned long long)am) - 1 : 0;
+            const int lane = (int)(threadIdx.x & (kWave - 1));
+            for (int L = 0; L < g.nlev && am; L++) {
+                const uint32_t gc = g.lv[L].base + c;
+                const uint32_t g0 = (uint32_t)__shfl((int)gc, leader, kWave);
+                const bool uni = __all(!act || gc == g0);
+                if (act && (!uni || lane == leader)) {
 #pragma unroll
-                for (int j = 0; j < kLev; j++) a.cellAlev[gc + j] = 0;
-                if (L + 1 < g.nlev) c = g.lv[L].parent[c];
+                    for (int j = 0; j < kLev; j++) a.cellAlev[(size_t)gc * kLev + j] = 0;
+                }
+                if (uni) {
+                    const uint32_t cnt = (uint32_t)__popcll(__ballot(rm));
+                    if (lane == leader && cnt) atomicSub(&a.cell_alive[g0], cnt);
+                } else if (rm) {
+                    atomicSub(&a.cell_alive[gc], 1u);
+                }
+                if (act && L + 1 < g.nlev) c = g.lv[L].parent[c];
             }
         }
         const uint32_t p = wave_append(&st->nR, rm);
@@ -467,11 +485,6 @@ __global__ void __launch_bounds__(kBlock) rb_remove(RoundArrays a, GridView g) {
             a.ev_orig[st->removed + p] = a.pts[x].w;
             a.alive[x] = 0;
             atomicSub(&a.seg_left[seg_of_pt(a, x)], 1u);
-            uint32_t c = a.of0[x];
-            for (int L = 0; L < g.nlev; L++) {
-                atomicSub(&a.cell_alive[g.lv[L].base + c], 1u);
-                if (L + 1 < g.nlev) c = g.lv[L].parent[c];
-            }
         }
     }
 }
@@ -957,8 +970,8 @@ int run_rounds(Ctx* c, RoundArrays& a, const GridView& g, uint32_t n) {
             fflush(stderr);
         }
         // rebuild the reverse lists when the appended chains overflowed or
-        // grew longer than three nodes per alive point on average
-        if (hst->overflow || hst->pool_count > 3 * hst->n_alive_new) {
+        // grew longer than six nodes per alive point on average
+        if (hst->overflow || hst->pool_count > 6 * hst->n_alive_new) {
             if ((rc = build_reverse(c, a, n))) return rc;
             c->stats[3]++;
         }
