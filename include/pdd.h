@@ -181,7 +181,8 @@ int pdd_autotune(pdd_ctx *ctx, const int32_t *d_xyz, int64_t n, int64_t keep, co
  *   rebuilds, 4 (unused, 0), 5 finest cell level (log2 mm), 6 list width used,
  *   7 touched (re-costed) points, 8 points tested by the initial k-NN search,
  *   9 predicted balls that certified a list, 10 predicted balls that did not
- *   (those points fell back to the shell search), 11 (unused, 0).
+ *   (those points fell back to the shell search), 11 points whose LDS tile
+ *   could not certify their list (searched again by the shell search).
  * Entries 8-10 are also written by pdd_knn_cost.
  * Returns the number of counters written. */
 int pdd_last_stats(const pdd_ctx *ctx, int64_t *stats, int n);

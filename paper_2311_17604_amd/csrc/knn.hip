@@ -8,6 +8,286 @@ namespace pdd {
 namespace {
 
 constexpr int kSlotKnnStat = 88;
+constexpr int kSlotTileAnc = 124, kSlotTileFlag = 125, kSlotTilePos = 126, kSlotTileList = 127,
+              kSlotTileFB = 100;
+constexpr int kTileCap = 2048;  // candidates of one tile held in LDS (11-bit index)
+
+// Anchor cell of every point (global cell id), and a flag per anchor cell.
+__global__ void __launch_bounds__(kBlock) tile_mark_k(GridView g, uint32_t need, uint32_t* __restrict__ anc_of,
+                                                      uint32_t* __restrict__ flag) {
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < g.n; j += gridDim.x * blockDim.x) {
+        int L;
+        uint32_t c;
+        anchor_cell(g, j, need, nullptr, &L, &c);
+        const uint32_t gid = g.lv[L].base + c;
+        anc_of[j] = gid;
+        flag[gid] = 1u;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) tile_list_k(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos,
+                                                      uint32_t total, uint32_t* __restrict__ tiles) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x)
+        if (flag[t]) tiles[pos[t]] = t;
+}
+
+// Packs the threads with pred set onto slots 0.. in thread order (block
+// wide; every thread must call it).  Returns the thread's slot; *count gets
+// the total after the call.
+__device__ inline uint32_t block_pack(bool pred, uint32_t* s_w, uint32_t* count) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const uint64_t m = __ballot(pred);
+    if (lane == 0) s_w[w] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int i = 0; i < kBlock / kWave; i++) {
+            const uint32_t v = s_w[i];
+            s_w[i] = acc;
+            acc += v;
+        }
+        *count = acc;
+    }
+    __syncthreads();
+    return s_w[w] + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
+// Squared distance from u to the nearest coordinate outside cells
+// [r0, r0 + w) (edge 2^s) along one axis, ignoring a side with no cell
+// beyond it; ~0 when neither side has one.
+__device__ inline uint64_t region_gap2(int u, int r0, int w, int s, int cmax) {
+    uint64_t g = ~0ull;
+    if (r0 - 1 >= 0) {
+        const uint64_t lo = (uint64_t)(u - (r0 << s) + 1);
+        g = lo * lo;
+    }
+    if (r0 + w <= cmax) {
+        const uint64_t hi = (uint64_t)(((r0 + w) << s) - u);
+        if (hi * hi < g) g = hi * hi;
+    }
+    return g;
+}
+
+// LDS-tiled k-NN: one block per anchor cell (the finest cell holding K + 1
+// points).  The block loads the points of the region around the cell into
+// LDS once: at level L >= 1 the 4x4x4 cells of level L-1 centred on it (the
+// cell and half its edge around it), at level 0 its 3x3x3 block.  Each
+// thread then takes one point anchored there and scans the whole region
+// from LDS, keeping its K smallest (d2, slot) keys in registers.  The list
+// is exact when its K-th distance is within the region's distance to the
+// nearest cell outside it; other points (and tiles whose region holds more
+// than kTileCap points) go to the fallback list for the wave search.
+template <int K>
+__global__ void __launch_bounds__(kBlock) knn_tile_k(GridView g, int k, const uint32_t* __restrict__ tiles,
+                                                     uint32_t ntiles, const uint32_t* __restrict__ anc_of,
+                                                     int32_t* __restrict__ nbr, uint8_t* __restrict__ cnt,
+                                                     uint64_t* __restrict__ cost, int64_t* __restrict__ r2k,
+                                                     uint32_t* __restrict__ fb, unsigned long long* __restrict__ stat) {
+    __shared__ int4 cand[kTileCap];
+    __shared__ uint32_t cst[kWave], cex[kWave + 1];
+    __shared__ uint32_t s_q[kBlock], s_pack[kBlock / kWave + 1], s_npack;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    uint32_t tested = 0, nfb = 0;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint32_t gid = tiles[t];
+        int L = 0;
+        while (L + 1 < g.nlev && gid >= g.lv[L + 1].base) L++;
+        const LevelView& lv = g.lv[L];
+        const uint32_t c = gid - lv.base;
+        const uint64_t code = lv.key[c];
+        const uint32_t sg = (uint32_t)(code >> lv.segshift);
+        const uint64_t mc = code & ((1ull << lv.segshift) - 1ull);
+        const int cx = (int)compact21(mc), cy = (int)compact21(mc >> 1), cz = (int)compact21(mc >> 2);
+        const int rl = L >= 1 ? L - 1 : 0, w = L >= 1 ? 4 : 3;
+        const LevelView& rv = g.lv[rl];
+        const int rx = L >= 1 ? 2 * cx - 1 : cx - 1, ry = L >= 1 ? 2 * cy - 1 : cy - 1, rz = L >= 1 ? 2 * cz - 1 : cz - 1;
+        // region cells: wave 0 looks them up and lays their points out
+        if (tid < kWave) {
+            uint32_t st = 0, n = 0;
+            if (lane < w * w * w) {
+                // the cells around the anchored points first (the 2x2x2 inner
+                // cells, or the centre cell), so that the lists fill with near
+                // points early and later candidates rarely enter
+                int cell = lane;
+                if (w == 4) {
+                    const int inner = (lane & 1) + 1, inner_y = ((lane >> 1) & 1) + 1, inner_z = ((lane >> 2) & 1) + 1;
+                    if (lane < 8) {
+                        cell = inner + 4 * inner_y + 16 * inner_z;
+                    } else {
+                        // the other 56 cells in order, skipping the inner ones
+                        int r = lane - 8, idx = 0;
+                        for (idx = 0; idx < 64; idx++) {
+                            const int ix = idx & 3, iy = (idx >> 2) & 3, iz = idx >> 4;
+                            const bool in = ix >= 1 && ix <= 2 && iy >= 1 && iy <= 2 && iz >= 1 && iz <= 2;
+                            if (!in && r-- == 0) break;
+                        }
+                        cell = idx;
+                    }
+                } else {
+                    cell = lane == 0 ? 13 : (lane <= 13 ? lane - 1 : lane);
+                }
+                const int x = rx + cell % w, y = ry + (cell / w) % w, z = rz + cell / (w * w);
+                if (x >= 0 && y >= 0 && z >= 0 && x <= rv.cmax[0] && y <= rv.cmax[1] && z <= rv.cmax[2]) {
+                    const uint32_t cc = hash_find(rv.hkeys, rv.hvals, rv.hmask, cell_code(rv, sg, x, y, z));
+                    if (cc != kNone) {
+                        st = rv.start[cc];
+                        n = rv.start[cc + 1] - st;
+                    }
+                }
+            }
+            uint32_t incl = n;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const uint32_t v = (uint32_t)__shfl_up((int)incl, o, kWave);
+                if (lane >= o) incl += v;
+            }
+            cst[lane] = st;
+            cex[lane] = incl - n;
+            if (lane == kWave - 1) cex[kWave] = incl;
+        }
+        __syncthreads();
+        const uint32_t total = cex[kWave];
+        const bool fits = total <= (uint32_t)kTileCap;
+        if (fits)
+            for (uint32_t u = tid; u < total; u += blockDim.x) {
+                int l = 0;
+#pragma unroll
+                for (int step = 32; step > 0; step >>= 1)
+                    if (cex[l + step] <= u) l += step;
+                const uint32_t j = cst[l] + (u - cex[l]);
+                const int4 p = g.pts[j];
+                cand[u] = make_int4(p.x, p.y, p.z, (int)j);
+            }
+        __syncthreads();
+        // the points anchored here, packed onto the first threads (waves
+        // past the last query skip the scan)
+        const uint32_t q0 = lv.start[c], q1 = lv.start[c + 1];
+        for (uint32_t qb = q0; qb < q1; qb += blockDim.x) {
+            const uint32_t qq = qb + tid;
+            const bool anch = qq < q1 && anc_of[qq] == gid;
+            const uint32_t slot = block_pack(anch, s_pack, &s_npack);
+            if (anch) s_q[slot] = qq;
+            __syncthreads();
+            const uint32_t nq = s_npack;
+            const bool mine = (uint32_t)tid < nq;
+            const uint32_t q = mine ? s_q[tid] : 0u;
+            __syncthreads();
+            if (!fits) {
+                if (mine) fb[atomicAdd(&stat[3], 1ull)] = q;
+                continue;
+            }
+            if ((uint32_t)(tid & ~(kWave - 1)) >= nq) continue;  // whole wave without a query
+            int4 qp = make_int4(0, 0, 0, 0);
+            if (mine) qp = g.pts[q];
+            uint64_t top[K];
+#pragma unroll
+            for (int e = 0; e < K; e++) top[e] = ~0ull;
+            // candidates below the lane's K-th key wait in a 4-entry buffer;
+            // the (wave-wide) sorted insertion runs when some lane's buffer
+            // is full, and at the end
+            uint64_t b0 = ~0ull, b1 = ~0ull, b2 = ~0ull, b3 = ~0ull;
+            int nb = 0;
+            auto insert = [&](uint64_t key) {
+                if (key < top[K - 1]) {
+#pragma unroll
+                    for (int e = K - 1; e > 0; e--) {
+                        if (key < top[e - 1]) top[e] = top[e - 1];
+                        else if (key < top[e]) top[e] = key;
+                    }
+                    if (key < top[0]) top[0] = key;
+                }
+            };
+            auto flush = [&]() {
+                if (nb > 0) insert(b0);
+                if (nb > 1) insert(b1);
+                if (nb > 2) insert(b2);
+                if (nb > 3) insert(b3);
+                nb = 0;
+            };
+            for (uint32_t u = 0; u < total; u++) {
+                const int4 p = cand[u];
+                const uint64_t key = (dist2(qp.x, qp.y, qp.z, p.x, p.y, p.z) << 11) | u;
+                if (mine && (uint32_t)p.w != q && key < top[K - 1]) {
+                    b3 = nb == 3 ? key : b3;
+                    b2 = nb == 2 ? key : b2;
+                    b1 = nb == 1 ? key : b1;
+                    b0 = nb == 0 ? key : b0;
+                    nb++;
+                }
+                if (__any(nb == 4)) flush();
+            }
+            flush();
+            if (!mine) continue;
+            tested += total;
+            int filled = 0;
+#pragma unroll
+            for (int e = 0; e < K; e++) filled += top[e] != ~0ull;
+            const int s = rv.s;
+            uint64_t gap = region_gap2(qp.x - g.minx, rx, w, s, rv.cmax[0]);
+            const uint64_t gy = region_gap2(qp.y - g.miny, ry, w, s, rv.cmax[1]);
+            const uint64_t gz = region_gap2(qp.z - g.minz, rz, w, s, rv.cmax[2]);
+            if (gy < gap) gap = gy;
+            if (gz < gap) gap = gz;
+            const bool ok = gap == ~0ull || (filled == K && (top[K - 1] >> 11) <= gap);
+            if (!ok) {
+                fb[atomicAdd(&stat[3], 1ull)] = q;
+                nfb++;
+                continue;
+            }
+            const int use = filled < k ? filled : k;
+            uint64_t wsum = 0, dk = 0;
+#pragma unroll
+            for (int e = 0; e < K; e++) {
+                const uint64_t d = top[e] >> 11;
+                if (e < use) wsum += cost_term(d);
+                if (e == use - 1) dk = d;
+                nbr[(size_t)q * K + e] = e < filled ? cand[top[e] & 2047u].w : -1;
+            }
+            cnt[q] = (uint8_t)filled;
+            cost[q] = wsum;
+            if (r2k) r2k[q] = (int64_t)dk;
+        }
+        __syncthreads();
+    }
+    // one atomic per thread that did work
+    if (tested) atomicAdd(&stat[0], (unsigned long long)tested);
+    (void)nfb;
+}
+
+// The wave search for a list of points (the tiles' fallbacks).
+template <int K>
+__global__ void __launch_bounds__(kBlock) knn_list_k(GridView g, int k, const uint32_t* __restrict__ list,
+                                                     const unsigned long long* __restrict__ nlist,
+                                                     int32_t* __restrict__ nbr, uint8_t* __restrict__ cnt,
+                                                     uint64_t* __restrict__ cost, int64_t* __restrict__ r2k,
+                                                     unsigned long long* __restrict__ stat) {
+    __shared__ uint32_t lds[kBlock / kWave][2][kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    uint32_t tested = 0;
+    const uint32_t m = (uint32_t)*nlist;
+    const uint32_t nw = gridDim.x * (kBlock / kWave);
+    for (uint32_t t = blockIdx.x * (kBlock / kWave) + w; t < m; t += nw) {
+        const uint32_t q = list[t];
+        const int4 qp = g.pts[q];
+        SearchCtx sc{nullptr};
+        uint64_t d;
+        int32_t id;
+        int La;
+        uint32_t ca;
+        anchor_cell(g, q, K + 1, nullptr, &La, &ca);
+        wave_knn<K, kAll>(g, q, qp, sc, K, La > 0 ? La - 1 : 0, d, id, lds[w][0], lds[w][1], &tested);
+        const int c = __popcll(__ballot(lane < K && d != ~0ull));
+        const int use = c < k ? c : k;
+        const uint64_t wsum = wave_sum64(lane < use ? cost_term(d) : 0ull);
+        if (lane < K) nbr[(size_t)q * K + lane] = id;
+        if (lane == use - 1 && r2k) r2k[q] = (int64_t)d;
+        if (lane == 0) {
+            cnt[q] = (uint8_t)c;
+            cost[q] = wsum;
+        }
+    }
+    if (lane == 0 && tested) atomicAdd(&stat[0], (unsigned long long)tested);
+}
 
 // One wavefront per query (see wave_knn).  With rhat2 (squared radius per
 // anchor cell, 0 = none) the search first tests the predicted ball and
@@ -78,6 +358,40 @@ __global__ void __launch_bounds__(kBlock) to_original_k(const int4* __restrict__
 
 }  // namespace
 
+// tiled search with wave-search fallbacks (no predictor)
+template <int K>
+int knn_tiled(Ctx* c, const GridView& g, int k, KnnOut out, unsigned long long* stat) {
+    const uint32_t total = g.total_cells;
+    uint32_t* anc_of = (uint32_t*)scratch(c, kSlotTileAnc, (size_t)g.n * 4);
+    uint32_t* flag = (uint32_t*)scratch(c, kSlotTileFlag, (size_t)(total + 1) * 4);
+    uint32_t* pos = (uint32_t*)scratch(c, kSlotTilePos, (size_t)(total + 1) * 4);
+    uint32_t* tiles = (uint32_t*)scratch(c, kSlotTileList, (size_t)std::max<uint32_t>(total, g.n) * 4);
+    if (!anc_of || !flag || !pos || !tiles) return PDD_ENOMEM;
+    int rc = fill_u32(c, flag, 0, total + 1);
+    if (rc) return rc;
+    const dim3 block(kBlock);
+    const unsigned gp = std::min<uint32_t>((g.n + kBlock - 1) / kBlock, 16384u);
+    hipLaunchKernelGGL(tile_mark_k, dim3(gp), block, 0, c->stream, g, (uint32_t)K + 1, anc_of, flag);
+    PDD_HIP(c, hipGetLastError());
+    if ((rc = exclusive_scan_u32(c, flag, pos, total, pos + total))) return rc;
+    hipLaunchKernelGGL(tile_list_k, dim3(std::min<uint32_t>((total + kBlock - 1) / kBlock, 16384u)), block, 0,
+                       c->stream, flag, pos, total, tiles);
+    PDD_HIP(c, hipGetLastError());
+    uint32_t* h = (uint32_t*)((char*)c->pinned + 3072);
+    PDD_HIP(c, hipMemcpyAsync(h, pos + total, 4, hipMemcpyDeviceToHost, c->stream));
+    PDD_HIP(c, hipStreamSynchronize(c->stream));
+    const uint32_t ntiles = h[0];
+    uint32_t* fb = (uint32_t*)scratch(c, kSlotTileFB, (size_t)g.n * 4);
+    if (!fb) return PDD_ENOMEM;
+    hipLaunchKernelGGL(knn_tile_k<K>, dim3(std::min<uint32_t>(std::max<uint32_t>(ntiles, 1u), 65535u)), block, 0,
+                       c->stream, g, k, tiles, ntiles, anc_of, out.nbr, out.cnt, out.cost, out.r2k, fb, stat);
+    PDD_HIP(c, hipGetLastError());
+    hipLaunchKernelGGL(knn_list_k<K>, dim3(2048), block, 0, c->stream, g, k, fb, stat + 3, out.nbr, out.cnt, out.cost,
+                       out.r2k, stat);
+    PDD_HIP(c, hipGetLastError());
+    return PDD_OK;
+}
+
 int knn_all(Ctx* c, const GridView& g, int k, int K, KnnOut out, int64_t* fallbacks) {
     if (fallbacks) *fallbacks = 0;
     unsigned long long* stat = (unsigned long long*)scratch(c, kSlotKnnStat, 4 * sizeof(unsigned long long));
@@ -87,21 +401,35 @@ int knn_all(Ctx* c, const GridView& g, int k, int K, KnnOut out, int64_t* fallba
     const uint64_t* r2 = nullptr;
     if (c->pred_on && c->pred_ready && (rc = pred_radii(c, g, K, &r2))) return rc;
     const dim3 wg(std::min<uint32_t>((g.n + 3) / 4, 16384u)), block(kBlock);
-    switch (K) {
-        case 8: hipLaunchKernelGGL(knn_wave_k<8>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k, r2, stat); break;
-        case 16: hipLaunchKernelGGL(knn_wave_k<16>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k, r2, stat); break;
-        case 24: hipLaunchKernelGGL(knn_wave_k<24>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k, r2, stat); break;
-        case 32: hipLaunchKernelGGL(knn_wave_k<32>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k, r2, stat); break;
-        default: return PDD_EINVAL;
+    if (r2) {
+        switch (K) {
+            case 8: hipLaunchKernelGGL(knn_wave_k<8>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k, r2, stat); break;
+            case 16: hipLaunchKernelGGL(knn_wave_k<16>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k, r2, stat); break;
+            case 24: hipLaunchKernelGGL(knn_wave_k<24>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k, r2, stat); break;
+            case 32: hipLaunchKernelGGL(knn_wave_k<32>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k, r2, stat); break;
+            default: return PDD_EINVAL;
+        }
+        PDD_HIP(c, hipGetLastError());
+    } else {
+        switch (K) {
+            case 8: rc = knn_tiled<8>(c, g, k, out, stat); break;
+            case 16: rc = knn_tiled<16>(c, g, k, out, stat); break;
+            case 24: rc = knn_tiled<24>(c, g, k, out, stat); break;
+            case 32: rc = knn_tiled<32>(c, g, k, out, stat); break;
+            default: return PDD_EINVAL;
+        }
+        if (rc) return rc;
     }
-    PDD_HIP(c, hipGetLastError());
-    // counters: points tested, predicted balls that certified, that did not
+    // counters: points tested, predicted balls that certified, that did
+    // not, tile points that fell back to the wave search
     unsigned long long* h = (unsigned long long*)c->pinned;
-    PDD_HIP(c, hipMemcpyAsync(h, stat, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+    PDD_HIP(c, hipMemcpyAsync(h, stat, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
     PDD_HIP(c, hipStreamSynchronize(c->stream));
     c->stats[8] = (int64_t)h[0];
     c->stats[9] = (int64_t)h[1];
     c->stats[10] = (int64_t)h[2];
+    c->stats[11] = (int64_t)h[3];
+    if (fallbacks) *fallbacks = (int64_t)h[3];
     return PDD_OK;
 }
 

@@ -19,7 +19,7 @@ PDD_F_PROGRESS = 4
 PHASES = ("grid", "knn", "reverse", "rounds", "final")
 
 STATS = ("rounds", "researches", "danger_checks", "reverse_rebuilds", "unused4", "voxel_log2",
-         "list_width", "touched", "knn_tested", "pred_hits", "pred_misses", "unused11")
+         "list_width", "touched", "knn_tested", "pred_hits", "pred_misses", "knn_fallbacks")
 PRED_NPARAM = 8385
 
 _lib = None
@@ -244,6 +244,19 @@ def decimate_batch(ctx: Context, xyz, offsets, keeps, k: int, b: int = 0, voxel_
 # ---------------------------------------------------------------------------
 # search-radius predictor
 # ---------------------------------------------------------------------------
+
+def pred_init(seed: int, out_bias: float = 0.0):
+    """Initial predictor parameters in the library's flat layout (W1 [64 in]
+    [64 out], b1, W2, b2, w3, b3): He-normal hidden weights, zero hidden
+    biases, small output weights, output bias `out_bias`."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    parts = [rng.normal(0, np.sqrt(2 / 64), 64 * 64), np.zeros(64), rng.normal(0, np.sqrt(2 / 64), 64 * 64),
+             np.zeros(64), rng.normal(0, 0.05, 64), np.array([out_bias])]
+    p = np.concatenate(parts).astype(np.float32)
+    assert p.shape == (PRED_NPARAM,)
+    return p
+
 
 def pred_set_weights(ctx: Context, params):
     """Set the predictor's PRED_NPARAM fp32 parameters (numpy array)."""
