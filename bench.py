@@ -74,6 +74,27 @@ def cpu_baseline(w, rows_cols):
 
 
 GRIDS = {1: (500, 400), 2: (5000, 4000)}
+PRED_MARGIN = 0.25
+
+
+def train_predictor(ctx, k, b):
+    """Trains the context's search-radius predictor for list width
+    list(k + b) on scans of the 200k-scan generator (seeds 101-104, half the
+    ray grid) and returns a summary."""
+    import torch
+
+    from paper_2311_17604_amd import pdd, scangen
+    feats, tgts = [], []
+    for seed in (101, 102, 103, 104):
+        wt = scangen.config(1, scale=0.5, seed=seed)
+        f, t = pdd.pred_samples(ctx, torch.from_numpy(wt.xyz).cuda(), k, b)
+        feats.append(f)
+        tgts.append(t)
+    feat, tgt = torch.cat(feats), torch.cat(tgts)
+    pdd.pred_set_weights(ctx, pdd.pred_init(11, float(tgt.mean().item())))
+    losses = pdd.pred_train(ctx, feat, tgt, steps=1500, batch=128, lr=2e-3, tau=0.9, seed=5).cpu().numpy()
+    return {"rows": int(feat.shape[0]), "loss_first": float(losses[:20].mean()),
+            "loss_last": float(losses[-100:].mean()), "margin_log2": PRED_MARGIN}
 
 
 def main():
@@ -89,6 +110,11 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (by default b, voxel and round share are chosen first by timed trials "
                          "on a sample; not timed, reported as config.autotune)")
+    ap.add_argument("--no-predictor", action="store_true",
+                    help="skip the learned search-radius bound (by default it is trained first on k-NN radii of "
+                         "scans from the 200k-scan generator, other seeds; not timed, reported as config.predictor)")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="do not also time the plain configuration (no predictor) for comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true", help="no per-50-round progress lines from the library")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -126,6 +152,12 @@ def main():
         tune["tune_s"] = round(time.time() - t_tune, 2)
         print("autotune: %s" % tune, file=sys.stderr, flush=True)
         args.b, args.voxel_log2, args.round_frac = tune["b"], tune["voxel_log2"], tune["round_frac"]
+    pred = None
+    if not args.no_predictor:
+        t_tr = time.time()
+        pred = train_predictor(ctx, w.k, args.b)
+        pred["train_s"] = round(time.time() - t_tr, 2)
+        print("predictor: %s" % pred, file=sys.stderr, flush=True)
     if batch:
         kw = dict(b=args.b, voxel_log2=args.voxel_log2, round_frac=args.round_frac, timing=True,
                   progress=not args.quiet)
@@ -137,18 +169,29 @@ def main():
         kw = dict(b=args.b, voxel_log2=args.voxel_log2, round_frac=args.round_frac, out=(kept, order, oc),
                   timing=True, progress=not args.quiet)
         run = lambda: pdd.decimate(ctx, x, w.keep, w.k, **kw)  # noqa: E731
-    for i in range(args.warmup):
-        run()
-        print("warmup %d done" % i, file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    phases = []
-    for i in range(args.steps):
-        run()
-        phases.append(ctx.timing())
-        print("step %d done %s" % (i, phases[-1]), file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+
+    def timed(label):
+        for i in range(args.warmup):
+            run()
+            print("%s warmup %d done" % (label, i), file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phases = []
+        for i in range(args.steps):
+            run()
+            phases.append(ctx.timing())
+            print("%s step %d done %s" % (label, i, phases[-1]), file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, phases
+
+    plain = None
+    if pred is not None and not args.no_plain:
+        pdd.pred_enable(ctx, False)
+        dtp, _ = timed("plain")
+        plain = {"value": n * args.steps / dtp, "ms_per_step": dtp * 1e3 / args.steps}
+    if pred is not None:
+        pdd.pred_enable(ctx, True, PRED_MARGIN)
+    dt, phases = timed("learned" if pred is not None else "plain")
     st = ctx.stats()
     ph = {p: round(sum(q[p] for q in phases) / len(phases), 3) for p in phases[0]}
 
@@ -184,8 +227,10 @@ def main():
         "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": workload, "n": n, "k": w.k, "keep": w.keep,
-                   "method": "batched" if batch else ("autotuned" if tune else "plain"),
-                   "clouds": int(len(w.keeps)) if batch else 1, "autotune": tune,
+                   "method": "+".join([m for m, on in (("batched", batch), ("autotuned", tune is not None),
+                                                        ("learned", pred is not None)) if on]) or "plain",
+                   "clouds": int(len(w.keeps)) if batch else 1, "autotune": tune, "predictor": pred,
+                   "plain": plain,
                    "gen_s": round(t_gen, 2), "stats": st, "phase_ms": ph},
         "roofline": roof,
         "cpu_baseline": cpu,

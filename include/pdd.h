@@ -180,9 +180,9 @@ int pdd_autotune(pdd_ctx *ctx, const int32_t *d_xyz, int64_t n, int64_t keep, co
  *   0 rounds, 1 re-searches (buffer exhausted), 2 danger checks, 3 reverse-list
  *   rebuilds, 4 (unused, 0), 5 finest cell level (log2 mm), 6 list width used,
  *   7 touched (re-costed) points, 8 points tested by the initial k-NN search,
- *   9 predicted balls that certified a list, 10 predicted balls that did not
- *   (those points fell back to the shell search), 11 points whose LDS tile
- *   could not certify their list (searched again by the shell search).
+ *   9 lists certified in predicted regions, 10 lists in predicted regions
+ *   that were not (searched again by the shell search), 11 points whose
+ *   tile could not certify their list (all searched again).
  * Entries 8-10 are also written by pdd_knn_cost.
  * Returns the number of counters written. */
 int pdd_last_stats(const pdd_ctx *ctx, int64_t *stats, int n);
@@ -195,19 +195,21 @@ int pdd_last_stats(const pdd_ctx *ctx, int64_t *stats, int n);
 int pdd_last_timing(const pdd_ctx *ctx, float *ms, int n);
 
 /*
- * Learned search-radius bound (not part of the paper; it bounds the k-NN
- * search of Sec. 5, which the paper does over the 26 voxels around a point's
- * own voxel).  Per anchor cell, the finest grid cell around a point holding
- * list-width + 1 points, a network predicts log2(r / cell edge), r an upper
- * bound on the list-width-th neighbour distance of the cell's points, from
- * 64 features: log1p of the point counts of the 4x4x4 cells of half the
- * edge centred on the cell.  The search then tests only the cells meeting
- * the ball of radius 2^margin * r and keeps the list when its last distance
- * lies inside the ball; otherwise it falls back to the shell search.  So the
- * predictor changes which points are tested, never a result.
- *
- * A network is trained for one list width (list(k + b) below) and bounds
- * the searches of that width.
+ * Learned search region (not part of the paper; it sizes the k-NN search of
+ * Sec. 5, which the paper does over the 26 voxels around a point's own
+ * voxel).  The initial k-NN runs in tiles, one per anchor cell: the finest
+ * grid cell around a point that holds list-width + 1 points.  A tile scans a
+ * region of cells around its anchor cell; by default the cell grown by half
+ * its edge.  A network predicts, per anchor cell, log2(e / cell edge), e the
+ * growth needed for the region to hold the list of every point anchored
+ * there (the list's last distance less the point's distance to the outside
+ * of the cell, maximised over the cell), from 64 features: log1p of the
+ * point counts of the 4x4x4 cells of half the edge centred on the cell.
+ * The tile then uses the cell grown by 2^margin * e when that region is
+ * smaller than the default one.  A list whose last distance is not within
+ * the region's distance to its outside is searched again by the shell
+ * search, so the predictor changes which points are tested, never a result.
+ * A network is trained for one list width (list(k + b) below).
  *
  * Network: 64 -> 64 -> 64 -> 1 with ReLU; PDD_PRED_NPARAM parameters in
  * fp32, flat: W1 [64 in][64 out], b1 [64], W2 [64][64], b2 [64], w3 [64],
@@ -225,17 +227,17 @@ int pdd_last_timing(const pdd_ctx *ctx, float *ms, int n);
 int pdd_pred_set_weights(pdd_ctx *ctx, const float *params, int64_t n);
 int pdd_pred_get_weights(pdd_ctx *ctx, float *params, int64_t n);
 
-/* Use (on != 0) or not the predicted radius in the initial k-NN of
+/* Use (on != 0) or not the predicted regions in the initial k-NN of
  * pdd_knn_cost and pdd_decimate; margin_log2 in [0, 8] is added to the
- * predicted log2 radius.  Errors: PDD_EINVAL (no parameters set). */
+ * predicted log2 growth.  Errors: PDD_EINVAL (no parameters set). */
 int pdd_pred_enable(pdd_ctx *ctx, int32_t on, float margin_log2);
 
 /* Training rows from a grid: runs the plain k-NN with list width
  * list(k + b), then for every anchor cell (level >= 1) writes its 64 bf16
  * features (d_feat [cap][64], uint16 bit patterns) and target
- * log2(sqrt(max d2 of its points' last list entry)) - log2(cell edge)
- * (d_target [cap] float; -8 when that distance is 0).  *count receives the
- * number of anchor cells; rows beyond cap are not written.
+ * log2(e) - log2(cell edge), e the growth described above in mm (d_target
+ * [cap] float; -8 when no growth is needed).  *count receives the number of
+ * anchor cells; rows beyond cap are not written.
  * Errors: PDD_EINVAL, PDD_ENOMEM, PDD_EHIP. */
 int pdd_pred_samples(pdd_ctx *ctx, const pdd_grid *grid, int32_t k, int32_t b, uint16_t *d_feat,
                      float *d_target, int64_t cap, int64_t *count);

@@ -11,6 +11,7 @@ constexpr int kSlotKnnStat = 88;
 constexpr int kSlotTileAnc = 124, kSlotTileFlag = 125, kSlotTilePos = 126, kSlotTileList = 127,
               kSlotTileFB = 100;
 constexpr int kTileCap = 2048;  // candidates of one tile held in LDS (11-bit index)
+constexpr int kTileCells = kBlock; // cells of one tile's region, at most
 
 // Anchor cell of every point (global cell id), and a flag per anchor cell.
 __global__ void __launch_bounds__(kBlock) tile_mark_k(GridView g, uint32_t need, uint32_t* __restrict__ anc_of,
@@ -80,14 +81,15 @@ __device__ inline uint64_t region_gap2(int u, int r0, int w, int s, int cmax) {
 template <int K>
 __global__ void __launch_bounds__(kBlock) knn_tile_k(GridView g, int k, const uint32_t* __restrict__ tiles,
                                                      uint32_t ntiles, const uint32_t* __restrict__ anc_of,
-                                                     int32_t* __restrict__ nbr, uint8_t* __restrict__ cnt,
-                                                     uint64_t* __restrict__ cost, int64_t* __restrict__ r2k,
-                                                     uint32_t* __restrict__ fb, unsigned long long* __restrict__ stat) {
+                                                     const uint64_t* __restrict__ rhat2, int32_t* __restrict__ nbr,
+                                                     uint8_t* __restrict__ cnt, uint64_t* __restrict__ cost,
+                                                     int64_t* __restrict__ r2k, uint32_t* __restrict__ fb,
+                                                     unsigned long long* __restrict__ stat) {
     __shared__ int4 cand[kTileCap];
-    __shared__ uint32_t cst[kWave], cex[kWave + 1];
-    __shared__ uint32_t s_q[kBlock], s_pack[kBlock / kWave + 1], s_npack;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1);
-    uint32_t tested = 0, nfb = 0;
+    __shared__ uint32_t cst[kTileCells], cex[kTileCells + 1];
+    __shared__ uint32_t s_q[kBlock], s_pack[kBlock / kWave + 1], s_npack, s_nin;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    uint32_t tested = 0, hits = 0, misses = 0;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const uint32_t gid = tiles[t];
         int L = 0;
@@ -97,63 +99,103 @@ __global__ void __launch_bounds__(kBlock) knn_tile_k(GridView g, int k, const ui
         const uint64_t code = lv.key[c];
         const uint32_t sg = (uint32_t)(code >> lv.segshift);
         const uint64_t mc = code & ((1ull << lv.segshift) - 1ull);
-        const int cx = (int)compact21(mc), cy = (int)compact21(mc >> 1), cz = (int)compact21(mc >> 2);
-        const int rl = L >= 1 ? L - 1 : 0, w = L >= 1 ? 4 : 3;
-        const LevelView& rv = g.lv[rl];
-        const int rx = L >= 1 ? 2 * cx - 1 : cx - 1, ry = L >= 1 ? 2 * cy - 1 : cy - 1, rz = L >= 1 ? 2 * cz - 1 : cz - 1;
-        // region cells: wave 0 looks them up and lays their points out
-        if (tid < kWave) {
-            uint32_t st = 0, n = 0;
-            if (lane < w * w * w) {
-                // the cells around the anchored points first (the 2x2x2 inner
-                // cells, or the centre cell), so that the lists fill with near
-                // points early and later candidates rarely enter
-                int cell = lane;
-                if (w == 4) {
-                    const int inner = (lane & 1) + 1, inner_y = ((lane >> 1) & 1) + 1, inner_z = ((lane >> 2) & 1) + 1;
-                    if (lane < 8) {
-                        cell = inner + 4 * inner_y + 16 * inner_z;
-                    } else {
-                        // the other 56 cells in order, skipping the inner ones
-                        int r = lane - 8, idx = 0;
-                        for (idx = 0; idx < 64; idx++) {
-                            const int ix = idx & 3, iy = (idx >> 2) & 3, iz = idx >> 4;
-                            const bool in = ix >= 1 && ix <= 2 && iy >= 1 && iy <= 2 && iz >= 1 && iz <= 2;
-                            if (!in && r-- == 0) break;
+        const int ac[3] = {(int)compact21(mc), (int)compact21(mc >> 1), (int)compact21(mc >> 2)};
+        // the region: by default the cells of level L-1 from half an edge
+        // below the anchor cell to half an edge above it (level 0: the
+        // 3x3x3 block); with a predicted radius r, the cells of the finest
+        // level at which the anchor cell grown by r spans at most 6 cells per
+        // axis, when they cover less than the default region
+        int rl = L >= 1 ? L - 1 : 0;
+        int r0[3], w[3];
+        for (int a = 0; a < 3; a++) {
+            r0[a] = L >= 1 ? 2 * ac[a] - 1 : ac[a] - 1;
+            w[a] = L >= 1 ? 4 : 3;
+        }
+        const uint64_t rp2 = (rhat2 && L >= 1) ? rhat2[gid] : 0ull;
+        if (rp2) {
+            const int r = (int)sqrt((double)rp2) + 1;
+            for (int l = 0; l <= L; l++) {
+                const int sl = g.lv[l].s;
+                bool ok = true;
+                int q0[3], qw[3];
+                for (int a = 0; a < 3; a++) {
+                    const int lo = max((ac[a] << lv.s) - r, 0), hi = (((ac[a] + 1) << lv.s) - 1) + r;
+                    q0[a] = lo >> sl;
+                    qw[a] = min(hi >> sl, g.lv[l].cmax[a]) - q0[a] + 1;
+                    if (qw[a] > 6) ok = false;
+                }
+                if (ok) {
+                    // taken only when smaller than the default region
+                    const int64_t vol = (int64_t)qw[0] * qw[1] * qw[2] << (3 * sl);
+                    const int64_t vdef = (int64_t)w[0] * w[1] * w[2] << (3 * g.lv[rl].s);
+                    if (vol < vdef) {
+                        rl = l;
+                        for (int a = 0; a < 3; a++) {
+                            r0[a] = q0[a];
+                            w[a] = qw[a];
                         }
-                        cell = idx;
                     }
-                } else {
-                    cell = lane == 0 ? 13 : (lane <= 13 ? lane - 1 : lane);
-                }
-                const int x = rx + cell % w, y = ry + (cell / w) % w, z = rz + cell / (w * w);
-                if (x >= 0 && y >= 0 && z >= 0 && x <= rv.cmax[0] && y <= rv.cmax[1] && z <= rv.cmax[2]) {
-                    const uint32_t cc = hash_find(rv.hkeys, rv.hvals, rv.hmask, cell_code(rv, sg, x, y, z));
-                    if (cc != kNone) {
-                        st = rv.start[cc];
-                        n = rv.start[cc + 1] - st;
-                    }
+                    break;
                 }
             }
-            uint32_t incl = n;
-#pragma unroll
-            for (int o = 1; o < kWave; o <<= 1) {
-                const uint32_t v = (uint32_t)__shfl_up((int)incl, o, kWave);
-                if (lane >= o) incl += v;
+        }
+        const LevelView& rv = g.lv[rl];
+        const int ncell = w[0] * w[1] * w[2];
+        // look the cells up (one per thread) and order them: cells that
+        // overlap the anchor cell first, so the lists fill with near points
+        // early and later candidates rarely enter
+        uint32_t st = 0, n = 0;
+        bool inner = false;
+        if (tid < ncell) {
+            const int ix = tid % w[0], iy = (tid / w[0]) % w[1], iz = tid / (w[0] * w[1]);
+            const int x = r0[0] + ix, y = r0[1] + iy, z = r0[2] + iz;
+            const int sh = lv.s - rv.s;
+            inner = (x >> sh) == ac[0] && (y >> sh) == ac[1] && (z >> sh) == ac[2];
+            if (x >= 0 && y >= 0 && z >= 0 && x <= rv.cmax[0] && y <= rv.cmax[1] && z <= rv.cmax[2]) {
+                const uint32_t cc = hash_find(rv.hkeys, rv.hvals, rv.hmask, cell_code(rv, sg, x, y, z));
+                if (cc != kNone) {
+                    st = rv.start[cc];
+                    n = rv.start[cc + 1] - st;
+                }
             }
-            cst[lane] = st;
-            cex[lane] = incl - n;
-            if (lane == kWave - 1) cex[kWave] = incl;
+        }
+        const uint32_t si = block_pack(tid < ncell && inner, s_pack, &s_nin);
+        const uint32_t so = block_pack(tid < ncell && !inner, s_pack, &s_npack);
+        if (tid < ncell) {
+            const uint32_t slot = inner ? si : s_nin + so;
+            cst[slot] = st;
+            cex[slot] = n;
         }
         __syncthreads();
-        const uint32_t total = cex[kWave];
+        // exclusive scan of the ordered counts (up to kTileCells = kBlock)
+        {
+            const uint32_t v = tid < ncell ? cex[tid] : 0u;
+            uint32_t incl = v;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const uint32_t u = (uint32_t)__shfl_up((int)incl, o, kWave);
+                if (lane >= o) incl += u;
+            }
+            if (lane == kWave - 1) s_pack[wv] = incl;
+            __syncthreads();
+            uint32_t base = 0;
+            for (int i = 0; i < wv; i++) base += s_pack[i];
+            cex[tid] = tid < ncell ? base + incl - v : 0xFFFFFFFFu;
+            if (tid == kBlock - 1) {
+                uint32_t tot = 0;
+                for (int i = 0; i < kBlock / kWave; i++) tot += s_pack[i];
+                cex[kTileCells] = tot;
+            }
+        }
+        __syncthreads();
+        const uint32_t total = cex[kTileCells];
         const bool fits = total <= (uint32_t)kTileCap;
         if (fits)
             for (uint32_t u = tid; u < total; u += blockDim.x) {
                 int l = 0;
 #pragma unroll
-                for (int step = 32; step > 0; step >>= 1)
-                    if (cex[l + step] <= u) l += step;
+                for (int step = kTileCells / 2; step > 0; step >>= 1)
+                    if (l + step < ncell && cex[l + step] <= u) l += step;
                 const uint32_t j = cst[l] + (u - cex[l]);
                 const int4 p = g.pts[j];
                 cand[u] = make_int4(p.x, p.y, p.z, (int)j);
@@ -174,6 +216,7 @@ __global__ void __launch_bounds__(kBlock) knn_tile_k(GridView g, int k, const ui
             __syncthreads();
             if (!fits) {
                 if (mine) fb[atomicAdd(&stat[3], 1ull)] = q;
+                if (mine && rp2) misses++;
                 continue;
             }
             if ((uint32_t)(tid & ~(kWave - 1)) >= nq) continue;  // whole wave without a query
@@ -223,15 +266,18 @@ __global__ void __launch_bounds__(kBlock) knn_tile_k(GridView g, int k, const ui
 #pragma unroll
             for (int e = 0; e < K; e++) filled += top[e] != ~0ull;
             const int s = rv.s;
-            uint64_t gap = region_gap2(qp.x - g.minx, rx, w, s, rv.cmax[0]);
-            const uint64_t gy = region_gap2(qp.y - g.miny, ry, w, s, rv.cmax[1]);
-            const uint64_t gz = region_gap2(qp.z - g.minz, rz, w, s, rv.cmax[2]);
+            uint64_t gap = region_gap2(qp.x - g.minx, r0[0], w[0], s, rv.cmax[0]);
+            const uint64_t gy = region_gap2(qp.y - g.miny, r0[1], w[1], s, rv.cmax[1]);
+            const uint64_t gz = region_gap2(qp.z - g.minz, r0[2], w[2], s, rv.cmax[2]);
             if (gy < gap) gap = gy;
             if (gz < gap) gap = gz;
             const bool ok = gap == ~0ull || (filled == K && (top[K - 1] >> 11) <= gap);
+            if (rp2) {
+                if (ok) hits++;
+                else misses++;
+            }
             if (!ok) {
                 fb[atomicAdd(&stat[3], 1ull)] = q;
-                nfb++;
                 continue;
             }
             const int use = filled < k ? filled : k;
@@ -249,9 +295,9 @@ __global__ void __launch_bounds__(kBlock) knn_tile_k(GridView g, int k, const ui
         }
         __syncthreads();
     }
-    // one atomic per thread that did work
     if (tested) atomicAdd(&stat[0], (unsigned long long)tested);
-    (void)nfb;
+    if (hits) atomicAdd(&stat[1], (unsigned long long)hits);
+    if (misses) atomicAdd(&stat[2], (unsigned long long)misses);
 }
 
 // The wave search for a list of points (the tiles' fallbacks).
@@ -360,7 +406,7 @@ __global__ void __launch_bounds__(kBlock) to_original_k(const int4* __restrict__
 
 // tiled search with wave-search fallbacks (no predictor)
 template <int K>
-int knn_tiled(Ctx* c, const GridView& g, int k, KnnOut out, unsigned long long* stat) {
+int knn_tiled(Ctx* c, const GridView& g, int k, KnnOut out, const uint64_t* rhat2, unsigned long long* stat) {
     const uint32_t total = g.total_cells;
     uint32_t* anc_of = (uint32_t*)scratch(c, kSlotTileAnc, (size_t)g.n * 4);
     uint32_t* flag = (uint32_t*)scratch(c, kSlotTileFlag, (size_t)(total + 1) * 4);
@@ -384,7 +430,7 @@ int knn_tiled(Ctx* c, const GridView& g, int k, KnnOut out, unsigned long long* 
     uint32_t* fb = (uint32_t*)scratch(c, kSlotTileFB, (size_t)g.n * 4);
     if (!fb) return PDD_ENOMEM;
     hipLaunchKernelGGL(knn_tile_k<K>, dim3(std::min<uint32_t>(std::max<uint32_t>(ntiles, 1u), 65535u)), block, 0,
-                       c->stream, g, k, tiles, ntiles, anc_of, out.nbr, out.cnt, out.cost, out.r2k, fb, stat);
+                       c->stream, g, k, tiles, ntiles, anc_of, rhat2, out.nbr, out.cnt, out.cost, out.r2k, fb, stat);
     PDD_HIP(c, hipGetLastError());
     hipLaunchKernelGGL(knn_list_k<K>, dim3(2048), block, 0, c->stream, g, k, fb, stat + 3, out.nbr, out.cnt, out.cost,
                        out.r2k, stat);
@@ -400,26 +446,14 @@ int knn_all(Ctx* c, const GridView& g, int k, int K, KnnOut out, int64_t* fallba
     if (rc) return rc;
     const uint64_t* r2 = nullptr;
     if (c->pred_on && c->pred_ready && (rc = pred_radii(c, g, K, &r2))) return rc;
-    const dim3 wg(std::min<uint32_t>((g.n + 3) / 4, 16384u)), block(kBlock);
-    if (r2) {
-        switch (K) {
-            case 8: hipLaunchKernelGGL(knn_wave_k<8>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k, r2, stat); break;
-            case 16: hipLaunchKernelGGL(knn_wave_k<16>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k, r2, stat); break;
-            case 24: hipLaunchKernelGGL(knn_wave_k<24>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k, r2, stat); break;
-            case 32: hipLaunchKernelGGL(knn_wave_k<32>, wg, block, 0, c->stream, g, k, out.nbr, out.cnt, out.cost, out.r2k, r2, stat); break;
-            default: return PDD_EINVAL;
-        }
-        PDD_HIP(c, hipGetLastError());
-    } else {
-        switch (K) {
-            case 8: rc = knn_tiled<8>(c, g, k, out, stat); break;
-            case 16: rc = knn_tiled<16>(c, g, k, out, stat); break;
-            case 24: rc = knn_tiled<24>(c, g, k, out, stat); break;
-            case 32: rc = knn_tiled<32>(c, g, k, out, stat); break;
-            default: return PDD_EINVAL;
-        }
-        if (rc) return rc;
+    switch (K) {
+        case 8: rc = knn_tiled<8>(c, g, k, out, r2, stat); break;
+        case 16: rc = knn_tiled<16>(c, g, k, out, r2, stat); break;
+        case 24: rc = knn_tiled<24>(c, g, k, out, r2, stat); break;
+        case 32: rc = knn_tiled<32>(c, g, k, out, r2, stat); break;
+        default: return PDD_EINVAL;
     }
+    if (rc) return rc;
     // counters: points tested, predicted balls that certified, that did
     // not, tile points that fell back to the wave search
     unsigned long long* h = (unsigned long long*)c->pinned;

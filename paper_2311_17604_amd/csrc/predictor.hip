@@ -1,13 +1,15 @@
 // Learned bound on the k-NN search radius.
 //
 // Sec. 5 searches a point's k+b neighbourhood in a fixed block of voxels
-// around it.  Here a small network predicts, per anchor cell (the finest cell
-// around a point that holds K+1 points), how far the K-th neighbour of its
-// points can be, from the occupancy of the 4x4x4 half-size cells around it.
-// The search then tests only the cells meeting that ball and keeps the
-// result when the K-th distance lies inside it (then it is exact: every
-// point within the ball was tested); otherwise it falls back to the shell
-// search.  The prediction can cost time but never changes a result.
+// around it.  Here the k-NN runs in tiles, one per anchor cell (the finest
+// cell around a point that holds K+1 points), over a region of cells around
+// it; a small network predicts, from the occupancy of the 4x4x4 half-size
+// cells around the anchor, by how much the anchor cell must be grown for the
+// region to hold every anchored point's K nearest.  The tile then loads only
+// that region (when it is smaller than the default one) and keeps a list
+// when its K-th distance lies inside the region (then it is exact: every
+// nearer point was tested); other points fall back to the shell search.
+// The prediction can cost time but never changes a result.
 //
 // Network: 64 -> 64 -> 64 -> 1 with ReLU, parameters flat in fp32
 // (W1 [64 in][64 out], b1, W2, b2, w3, b3); the two 64x64 products run on
@@ -80,10 +82,15 @@ __device__ inline float col_sum4(float v) {
 // anchors, features, targets
 // ---------------------------------------------------------------------------
 
-// Marks the anchor cell (level >= 1) of every point; with dK, also the
-// largest K-th neighbour distance of the points anchored there.
+// Marks the anchor cell (level >= 1) of every point.  With dK (squared
+// distance to the point's K-th neighbour), also the expansion of the anchor
+// cell that the point needs: its K-th distance (rounded up) less its
+// distance to the nearest coordinate outside the cell, maximised over the
+// cell's points into tmax (non-negative; 0 when every point's list lies
+// inside the cell).  A tile whose region is the anchor cell grown by that
+// much certifies all its points.
 __global__ void __launch_bounds__(kBlock) pr_mark_k(GridView g, uint32_t need, uint32_t* __restrict__ flag,
-                                                    const uint64_t* __restrict__ dK, uint64_t* __restrict__ tmax) {
+                                                    const uint64_t* __restrict__ dK, int64_t* __restrict__ tmax) {
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < g.n; j += gridDim.x * blockDim.x) {
         int L;
         uint32_t c;
@@ -91,7 +98,23 @@ __global__ void __launch_bounds__(kBlock) pr_mark_k(GridView g, uint32_t need, u
         if (L < 1) continue;
         const uint32_t gid = g.lv[L].base + c;
         flag[gid] = 1u;
-        if (dK) atomicMax((unsigned long long*)&tmax[gid], (unsigned long long)dK[j]);
+        if (dK) {
+            const uint64_t d2 = dK[j];
+            uint64_t r = (uint64_t)sqrt((double)d2);
+            while (r * r < d2) r++;
+            while (r > 0 && (r - 1) * (r - 1) >= d2) r--;
+            const int4 p = g.pts[j];
+            const int s = g.lv[L].s;
+            const int u[3] = {p.x - g.minx, p.y - g.miny, p.z - g.minz};
+            int64_t face = INT64_MAX;
+            for (int a = 0; a < 3; a++) {
+                const int cc = u[a] >> s;
+                const int64_t lo = (int64_t)u[a] - ((int64_t)cc << s) + 1, hi = ((int64_t)(cc + 1) << s) - u[a];
+                face = min(face, min(lo, hi));
+            }
+            const int64_t e = (int64_t)r - face;
+            if (e > 0) atomicMax((long long*)&tmax[gid], (long long)e);
+        }
     }
 }
 
@@ -110,9 +133,9 @@ __device__ inline int level_of_gid(const GridView& g, uint32_t gid) {
 // One wavefront per anchor cell (level L >= 1, coordinates c): lane
 // (dx, dy, dz) in 0..3 counts the points of the level L-1 cell
 // 2c + (dx, dy, dz) - 1; feature = log1p(count) in bf16.  With tmax, also
-// the target log2(sqrt(max dK) / 2^s_L) (-8 when every distance is 0).
+// the target log2(expansion / 2^s_L) (-8 when no expansion is needed).
 __global__ void __launch_bounds__(kBlock) pr_feat_k(GridView g, const uint32_t* __restrict__ anc, uint32_t nanc,
-                                                    uint16_t* __restrict__ feat, const uint64_t* __restrict__ tmax,
+                                                    uint16_t* __restrict__ feat, const int64_t* __restrict__ tmax,
                                                     float* __restrict__ target) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     for (uint32_t t = blockIdx.x * (kBlock / kWave) + w; t < nanc; t += gridDim.x * (kBlock / kWave)) {
@@ -132,8 +155,8 @@ __global__ void __launch_bounds__(kBlock) pr_feat_k(GridView g, const uint32_t* 
         }
         feat[(size_t)t * kF + lane] = to_bf16(log1pf((float)cnt));
         if (tmax && lane == 0) {
-            const uint64_t m = tmax[gid];
-            target[t] = m == 0 ? -8.0f : 0.5f * log2f((float)m) - (float)lv.s;
+            const int64_t m = tmax[gid];
+            target[t] = m <= 0 ? -8.0f : fmaxf(log2f((float)m) - (float)lv.s, -8.0f);
         }
     }
 }
@@ -451,7 +474,7 @@ __global__ void __launch_bounds__(kBlock) pr_train_k(const uint16_t* __restrict_
     }
 }
 
-// squared search radius per anchor cell: (2^(yhat + margin) * 2^s)^2, rounded up
+// squared expansion per anchor cell: (2^(yhat + margin) * 2^s)^2, rounded up
 __global__ void __launch_bounds__(kBlock) pr_radius_k(GridView g, const uint32_t* __restrict__ anc, uint32_t nanc,
                                                       const float* __restrict__ yhat, float margin,
                                                       uint64_t* __restrict__ r2) {
@@ -473,7 +496,7 @@ inline unsigned gfor(size_t count) {
 enum { kPrFlag = 76, kPrPos, kPrAnc, kPrFeat, kPrY, kPrR2, kPrTmax, kPrDK, kPrNbr, kPrCnt, kPrCost, kPrGrad };
 
 // anchor cells of every point, compacted; returns their count in *nanc
-int anchors(Ctx* c, const GridView& g, uint32_t need, const uint64_t* dK, uint64_t* tmax, uint32_t** anc_out,
+int anchors(Ctx* c, const GridView& g, uint32_t need, const uint64_t* dK, int64_t* tmax, uint32_t** anc_out,
             uint32_t* nanc) {
     const uint32_t total = g.total_cells;
     uint32_t* flag = (uint32_t*)scratch(c, kPrFlag, (size_t)(total + 1) * 4);
@@ -579,7 +602,7 @@ int pred_samples(Ctx* c, const GridView& g, int k, int K, uint16_t* feat, float*
     ko.cost = (uint64_t*)scratch(c, kPrCost, (size_t)g.n * 8);
     ko.r2k = nullptr;
     uint64_t* dK = (uint64_t*)scratch(c, kPrDK, (size_t)g.n * 8);
-    uint64_t* tmax = (uint64_t*)scratch(c, kPrTmax, (size_t)(g.total_cells + 1) * 8);
+    int64_t* tmax = (int64_t*)scratch(c, kPrTmax, (size_t)(g.total_cells + 1) * 8);
     if (!ko.nbr || !ko.cnt || !ko.cost || !dK || !tmax) return PDD_ENOMEM;
     const bool on = c->pred_on;
     c->pred_on = false;  // samples come from the plain search
