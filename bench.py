@@ -8,11 +8,13 @@ and round share by timed trials on a strided sample (not timed; reported in
 config.autotune; the settings never change the result).  Prints one JSON
 line with
 
-  roofline      the k-NN cost kernel: algorithmic bytes per launch (read one
-                16-byte point, write its K-entry list, cost and count) over
-                its average duration from HIP events recorded on the
-                library's stream; traffic from the rocprofv3 counter summary
-                in profiles/ when it matches the kernel source;
+  roofline      the k-NN cost phase (the LDS-tiled kernel knn_tile_k plus the
+                shell search of its few uncertified points, knn_list_k):
+                algorithmic bytes per launch (read one 16-byte point, write
+                its K-entry list, cost and count) over the phase's duration
+                from HIP events recorded on the library's stream; traffic
+                from the rocprofv3 counter summary in profiles/ when it
+                matches the workload, list width and kernel source;
   cpu_baseline  the CPU oracle (one core) on a bounded window of the same
                 scan.
 """
@@ -202,7 +204,7 @@ def main():
     knn_ms = ph["knn"]
     achieved = algo / (knn_ms * 1e-3) / 1e9
     workload = w.name if args.scale == 1.0 else "%s@%g" % (w.name, args.scale)
-    kname = "knn_wave_k<%d>" % K
+    kname = "knn_tile_k<%d>+knn_list_k<%d>" % (K, K)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(workload, kname),
             "kernel": kname, "algorithmic_bytes_per_launch": algo,
