@@ -109,6 +109,7 @@ def main():
     ap.add_argument("--round-frac", type=float, default=0.0)
     ap.add_argument("--voxel-log2", type=int, default=0)
     ap.add_argument("--b", type=int, default=0)
+    ap.add_argument("--round-blocks", type=int, default=0, help="workgroups per round-kernel launch (0: library default)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (by default b, voxel and round share are chosen first by timed trials "
                          "on a sample; not timed, reported as config.autotune)")
@@ -162,14 +163,14 @@ def main():
         print("predictor: %s" % pred, file=sys.stderr, flush=True)
     if batch:
         kw = dict(b=args.b, voxel_log2=args.voxel_log2, round_frac=args.round_frac, timing=True,
-                  progress=not args.quiet)
+                  progress=not args.quiet, round_blocks=args.round_blocks)
         run = lambda: pdd.decimate_batch(ctx, x, w.offsets, w.keeps, w.k, **kw)  # noqa: E731
     else:
         kept = torch.empty(w.keep, dtype=torch.int32, device="cuda")
         order = torch.empty(n - w.keep, dtype=torch.int32, device="cuda")
         oc = torch.empty(n - w.keep, dtype=torch.int64, device="cuda")
         kw = dict(b=args.b, voxel_log2=args.voxel_log2, round_frac=args.round_frac, out=(kept, order, oc),
-                  timing=True, progress=not args.quiet)
+                  timing=True, progress=not args.quiet, round_blocks=args.round_blocks)
         run = lambda: pdd.decimate(ctx, x, w.keep, w.k, **kw)  # noqa: E731
 
     def timed(label):

@@ -64,7 +64,9 @@ typedef struct {
                                adapted per round between 1e-5 and 4x the initial value */
     int32_t point_stride;   /* bytes between points: 12 or 16 (default 12) */
     int32_t flags;          /* PDD_F_* bits */
-    int32_t reserved[4];
+    int32_t round_blocks;   /* workgroups (256 threads) per launch of the removal-round kernels, 64..65535
+                               (default 1024); the kernels loop over their items, so results never depend on it */
+    int32_t reserved[3];
 } pdd_opts;
 
 #define PDD_F_CHECK 1       /* extra device-side invariant checks (slower) */
@@ -176,13 +178,14 @@ int pdd_autotune(pdd_ctx *ctx, const int32_t *d_xyz, int64_t n, int64_t keep, co
                  int64_t sample, pdd_opts *out, float *best_ms);
 
 /* Counters of the last pdd_decimate on this context, written to stats[0..n),
- * n <= 12:
+ * n <= 14:
  *   0 rounds, 1 re-searches (buffer exhausted), 2 danger checks, 3 reverse-list
  *   rebuilds, 4 (unused, 0), 5 finest cell level (log2 mm), 6 list width used,
  *   7 touched (re-costed) points, 8 points tested by the initial k-NN search,
  *   9 lists certified in predicted regions, 10 lists in predicted regions
  *   that were not (searched again by the shell search), 11 points whose
- *   tile could not certify their list (all searched again).
+ *   tile could not certify their list (all searched again), 12 points tested
+ *   by the re-searches, 13 survivors enumerated by the danger checks.
  * Entries 8-10 are also written by pdd_knn_cost.
  * Returns the number of counters written. */
 int pdd_last_stats(const pdd_ctx *ctx, int64_t *stats, int n);

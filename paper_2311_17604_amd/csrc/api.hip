@@ -193,7 +193,9 @@ int pdd::decimate_entry(Ctx* c, const int32_t* d_xyz, int64_t n, const int64_t* 
     const int stride = opts->point_stride == 0 ? 12 : opts->point_stride;
     if (stride != 12 && stride != 16) return PDD_EINVAL;
     if (opts->voxel_log2 != 0 && (opts->voxel_log2 < 2 || opts->voxel_log2 > 20)) return PDD_EINVAL;
+    if (opts->round_blocks != 0 && (opts->round_blocks < 64 || opts->round_blocks > 65535)) return PDD_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return PDD_EHIP;
+    c->round_blocks = opts->round_blocks == 0 ? 1024u : (unsigned)opts->round_blocks;
     for (auto& s : c->stats) s = 0;
     for (auto& t : c->phase_ms) t = 0.0f;
     c->timing = (opts->flags & PDD_F_TIMING) != 0;
@@ -269,7 +271,7 @@ int pdd_decimate_batch(pdd_ctx* ctx, const int32_t* d_xyz, const int64_t* h_offs
 
 int pdd_last_stats(const pdd_ctx* ctx, int64_t* stats, int n) {
     if (!ctx || !stats || n < 0) return 0;
-    int m = n < 12 ? n : 12;
+    int m = n < pdd::kNumStats ? n : pdd::kNumStats;
     for (int i = 0; i < m; i++) stats[i] = ctx->c.stats[i];
     return m;
 }

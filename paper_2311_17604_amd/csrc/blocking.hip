@@ -21,6 +21,7 @@ __global__ void __launch_bounds__(kBlock) rb_pair(RoundArrays a) {
     const int k = a.k;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const uint32_t nw = gridDim.x * (kBlock / kWave);
+    uint32_t ndanger = 0;  // danger entries of this wave (wave-uniform)
     for (uint32_t t = blockIdx.x * (kBlock / kWave) + w; t < nA; t += nw) {
         const uint32_t y = a.A[t];
         const int4 py = a.pts[y];
@@ -78,7 +79,10 @@ __global__ void __launch_bounds__(kBlock) rb_pair(RoundArrays a) {
         if (lower && (q < k || !covered)) a.blocked[z] = round;
         // lower points beyond the list
         const int nL = __popcll(__ballot(cls == 1)), nAe = __popcll(__ballot(cls == 2));
-        if (!complete && nL < k) {
+        const bool danger = !complete && nL < k;
+        if (lane == 0 && !danger) a.dg_y[t] = kNone;
+        if (danger) {
+            ndanger++;
             const int need = k - nL;
             uint64_t tc = cy;
             int32_t to = oy;
@@ -89,15 +93,16 @@ __global__ void __launch_bounds__(kBlock) rb_pair(RoundArrays a) {
                 tc = readlane64(cj, l);
                 to = __builtin_amdgcn_readlane(oj, l);
             }
+            // the danger entry sits at y's position in A (no shared counter)
             if (lane == 0) {
-                const uint32_t p = atomicAdd(&st->nDanger, 1u);
-                a.dg_y[p] = y;
-                a.dg_tc[p] = tc;
-                a.dg_to[p] = to;
-                a.dg_dlast[p] = dlast;
+                a.dg_y[t] = y;
+                a.dg_tc[t] = tc;
+                a.dg_to[t] = to;
+                a.dg_dlast[t] = dlast;
             }
         }
     }
+    if (lane == 0 && ndanger) atomicAdd(&st->nDanger, ndanger);
 }
 
 // x in A with at least k alive points of identical coordinates ranked below
@@ -313,12 +318,15 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
     __shared__ uint64_t s_yc[W][K];
     __shared__ int32_t s_yo[W][K];
     __shared__ int s_ycls[W][K];
-    const uint32_t nd = st->nDanger, round = st->round, ns = st->nSurv;
+    // the danger entries are at their points' positions in A; kNone elsewhere
+    const uint32_t nd = st->nA, round = st->round, ns = st->nSurv;
     const int k = a.k, Kb = a.K;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const uint32_t nw = gridDim.x * W;
+    uint32_t enumerated = 0;  // survivors this wave enumerated (wave-uniform)
     for (uint32_t t = blockIdx.x * W + w; t < nd; t += nw) {
         const uint32_t y = a.dg_y[t];
+        if (y == kNone) continue;
         const uint64_t tc = a.dg_tc[t], dlast = a.dg_dlast[t];
         const int32_t to = a.dg_to[t];
         const uint64_t cy = a.cost[y];
@@ -457,7 +465,7 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
                 }
                 const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
                 if (total == 0) continue;
-                if (lane == 0) atomicAdd(&st->work, total);
+                enumerated += total;
                 s_start[w][lane] = st0;
                 s_excl[w][lane] = incl - cnt;
                 wave_sync_lds();
@@ -476,12 +484,16 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
         }
         wave_sync_lds();
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&st->stat_danger, nd);
+    if (lane == 0 && enumerated) {
+        atomicAdd(&st->work, enumerated);
+        atomicAdd(&st->stat_enum, (unsigned long long)enumerated);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&st->stat_danger, st->nDanger);
 }
 
 template <int K>
 int launch_k(Ctx* c, const RoundArrays& a, const GridView& g) {
-    const unsigned G = 1024;
+    const unsigned G = c->round_blocks;
     hipLaunchKernelGGL(rb_group, dim3(G), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_pair<K>, dim3(G), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_survive, dim3(G), dim3(kBlock), 0, c->stream, a, g);

@@ -19,6 +19,7 @@ constexpr int kSelBins0 = 4160;     // first-level bins of the threshold select 
 constexpr int kSelBins = 4096;      // refinement bins (12-bit digits)
 constexpr int kSelFinal = 2048;     // candidates resolved by one block sort
 constexpr int kScratchSlots = 128;  // scratch buffers of a context
+constexpr int kNumStats = 14;       // counters reported by pdd_last_stats
 
 // ---------------------------------------------------------------------------
 // small device helpers
@@ -177,7 +178,7 @@ struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
-    int64_t stats[12] = {0};
+    int64_t stats[kNumStats] = {0};
     // scratch pool: grow-only buffers keyed by slot
     struct Buf { void* p = nullptr; size_t bytes = 0; };
     Buf bufs[kScratchSlots];
@@ -185,6 +186,7 @@ struct Ctx {
     // phase timing (PDD_F_TIMING): events recorded on the context's stream
     bool timing = false;
     bool progress = false;    // PDD_F_PROGRESS: a line to stderr every 50 rounds
+    unsigned round_blocks = 1024;  // workgroups per launch of the round kernels
     hipEvent_t ev[8] = {};
     float phase_ms[8] = {0};
     // search-radius predictor: fp32 parameters and Adam moments (device)

@@ -24,6 +24,8 @@ struct RoundDev {
     float frac_max;
     uint32_t work;                // survivors enumerated by the danger checks, this round
     uint32_t pad3;
+    unsigned long long stat_rtested;  // points looked at by the re-searches, all rounds
+    unsigned long long stat_enum;     // survivors enumerated by the danger checks, all rounds
     uint64_t surv_min[kLev];      // lowest survivor cost per key level, this round
 };
 
@@ -45,7 +47,6 @@ struct RoundArrays {
     uint64_t* dg_tc;
     int32_t* dg_to;
     uint64_t* dg_dlast;
-    uint32_t* touch_list;
     uint32_t* research_list;
     uint32_t* R;
     uint64_t* ev_cost;

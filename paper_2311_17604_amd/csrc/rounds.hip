@@ -34,6 +34,7 @@
 // points.
 #include <stdio.h>
 
+#include <algorithm>
 #include <type_traits>
 #include <vector>
 
@@ -194,7 +195,7 @@ __global__ void __launch_bounds__(kBlock) rb_collect0(RoundArrays a, int par) {
     if (st->done || st->err) return;
     const uint32_t na = st->n_alive, bsel = st->sel_bin, round = st->round, mode = st->mode;
     const uint32_t* L = a.alive_list[par];
-    constexpr int IPT = 8;
+    constexpr int IPT = 32;  // items per thread: one shared-counter atomic per 8192 items
     for (uint32_t base = blockIdx.x * kBlock * IPT; base < na; base += gridDim.x * kBlock * IPT) {
         uint32_t item[IPT];
         uint32_t selA = 0, selC = 0, nA = 0, nC = 0;
@@ -504,60 +505,131 @@ __global__ void rb_remove_end(RoundArrays a) {
     else if (yield > 0.2f && st->work < (1u << 20)) st->frac = fminf(st->frac * 1.5f, st->frac_max);
 }
 
-__device__ inline void touch(const RoundArrays& a, RoundDev* st, uint32_t z, uint32_t round) {
-    if (!a.alive[z]) return;
-    if (atomicExch(&a.touched[z], round) == round) return;
-    const uint32_t p = atomicAdd(&st->nTouch, 1u);
-    a.touch_list[p] = z;
-}
-
-__global__ void __launch_bounds__(kBlock) rb_touch(RoundArrays a) {
+// Re-costs every alive point whose list held a removed point (the removed
+// points' reverse lists): one wavefront per 64 removed points.  Points
+// touched first by this wave are staged in its LDS and re-costed 64 at a
+// time, one per lane, from their lists' first k alive entries; a list with
+// fewer alive entries than k that did not hold every alive point is queued
+// for the re-search (staged as well: one shared-counter atomic per 64).
+__global__ void __launch_bounds__(kBlock) rb_touch_recost(RoundArrays a) {
     RoundDev* st = a.st;
     if (st->done || st->err) return;
+    constexpr int W = kBlock / kWave;
+    __shared__ uint32_t s_touch[W][2 * kWave], s_rs[W][2 * kWave], s_cnt[W];
     const uint32_t nR = st->nR, round = st->round;
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nR; t += gridDim.x * blockDim.x) {
-        const uint32_t x = a.R[t];
-        for (uint32_t e = a.rev_off[x]; e < a.rev_off[x + 1]; e++) touch(a, st, (uint32_t)a.rev_src[e], round);
-        for (int32_t p = a.head[x]; p >= 0; p = a.pool_next[p]) touch(a, st, (uint32_t)a.pool_src[p], round);
-    }
-}
-
-// Cost from the list's first k alive entries; a list with fewer alive
-// entries than k that did not hold every alive point is searched again.
-__global__ void __launch_bounds__(kBlock) rb_recost(RoundArrays a) {
-    RoundDev* st = a.st;
-    if (st->done || st->err) return;
-    const uint32_t nt = st->nTouch;
     const int K = a.K, k = a.k;
-    const uint32_t n_it = (nt + blockDim.x - 1) / blockDim.x * blockDim.x;
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_it; t += gridDim.x * blockDim.x) {
+    const int lane = (int)lane_id(), w = threadIdx.x / kWave;
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint32_t nt = 0, nrs = 0, ntouched = 0;  // wave-uniform
+    // re-cost s_touch[w][0, m)
+    auto recost = [&](uint32_t m) {
         bool rs = false;
         uint32_t z = 0;
-        if (t < nt) {
-            z = a.touch_list[t];
+        if ((uint32_t)lane < m) {
+            z = s_touch[w][lane];
             const int4 pz = a.pts[z];
             const int c = a.cnt[z];
             const int32_t* nb = a.nbr + (size_t)z * K;
             int valid = 0;
-            uint64_t w = 0;
+            uint64_t wsum = 0;
             for (int j = 0; j < c && valid < k; j++) {
                 const uint32_t y = (uint32_t)nb[j];
                 if (!a.alive[y]) continue;
                 const int4 py = a.pts[y];
-                w += cost_term(dist2(pz.x, pz.y, pz.z, py.x, py.y, py.z));
+                wsum += cost_term(dist2(pz.x, pz.y, pz.z, py.x, py.y, py.z));
                 valid++;
             }
             if (valid < k && c == K) {
                 rs = true;
             } else {
-                if (a.check && w > a.cost[z]) st->err = 6;
-                a.cost[z] = w;
+                if (a.check && wsum > a.cost[z]) st->err = 6;
+                a.cost[z] = wsum;
             }
         }
-        const uint32_t p = wave_append(&st->nResearch, rs);
-        if (rs) a.research_list[p] = z;
+        const uint64_t bm = __ballot(rs);
+        if (rs) s_rs[w][nrs + (uint32_t)__popcll(bm & below)] = z;
+        nrs += (uint32_t)__popcll(bm);
+        wave_sync_lds();
+        if (nrs >= (uint32_t)kWave) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&st->nResearch, (uint32_t)kWave);
+            base = (uint32_t)__shfl((int)base, 0, kWave);
+            a.research_list[base + lane] = s_rs[w][lane];
+            const uint32_t rem = nrs - kWave;
+            const uint32_t v = (uint32_t)lane < rem ? s_rs[w][kWave + lane] : 0u;
+            wave_sync_lds();
+            if ((uint32_t)lane < rem) s_rs[w][lane] = v;
+            nrs = rem;
+            wave_sync_lds();
+        }
+    };
+    // stage the lanes' newly touched points; re-cost once 64 are waiting
+    auto stage = [&](bool fresh, uint32_t z) {
+        const uint64_t m = __ballot(fresh);
+        if (fresh) s_touch[w][nt + (uint32_t)__popcll(m & below)] = z;
+        nt += (uint32_t)__popcll(m);
+        ntouched += (uint32_t)__popcll(m);
+        wave_sync_lds();
+        if (nt >= (uint32_t)kWave) {
+            recost(kWave);
+            const uint32_t rem = nt - kWave;
+            const uint32_t v = (uint32_t)lane < rem ? s_touch[w][kWave + lane] : 0u;
+            wave_sync_lds();
+            if ((uint32_t)lane < rem) s_touch[w][lane] = v;
+            nt = rem;
+            wave_sync_lds();
+        }
+    };
+    const uint32_t stride = gridDim.x * W * kWave;
+    for (uint32_t base = (blockIdx.x * W + w) * kWave; base < nR; base += stride) {
+        const uint32_t t = base + (uint32_t)lane;
+        uint32_t e = 0, e1 = 0;
+        int32_t p = -1;
+        if (t < nR) {
+            const uint32_t x = a.R[t];
+            e = a.rev_off[x];
+            e1 = a.rev_off[x + 1];
+            p = a.head[x];
+        }
+        // reverse entries in the CSR part, then in the appended chains
+        while (__ballot(e < e1)) {
+            bool fresh = false;
+            uint32_t z = 0;
+            if (e < e1) {
+                z = (uint32_t)a.rev_src[e++];
+                fresh = a.alive[z] && atomicExch(&a.touched[z], round) != round;
+            }
+            stage(fresh, z);
+        }
+        while (__ballot(p >= 0)) {
+            bool fresh = false;
+            uint32_t z = 0;
+            if (p >= 0) {
+                z = (uint32_t)a.pool_src[p];
+                p = a.pool_next[p];
+                fresh = a.alive[z] && atomicExch(&a.touched[z], round) != round;
+            }
+            stage(fresh, z);
+        }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&st->stat_touch, nt);
+    if (nt) recost(nt);
+    if (nrs) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&st->nResearch, nrs);
+        base = (uint32_t)__shfl((int)base, 0, kWave);
+        if ((uint32_t)lane < nrs) a.research_list[base + lane] = s_rs[w][lane];
+    }
+    // touched count: one atomic per block
+    if (lane == 0) s_cnt[w] = ntouched;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t sum = 0;
+        for (int i = 0; i < W; i++) sum += s_cnt[i];
+        if (sum) {
+            atomicAdd(&st->nTouch, sum);
+            atomicAdd(&st->stat_touch, sum);
+        }
+    }
 }
 
 // New list of z over the alive points: one wavefront per point.
@@ -570,6 +642,8 @@ __global__ void __launch_bounds__(kBlock) rb_research(RoundArrays a, GridView g)
     const int k = a.k;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const uint32_t nw = gridDim.x * (kBlock / kWave);
+    const uint32_t pool_base = st->pool_count;
+    uint32_t tested = 0;
     for (uint32_t t = blockIdx.x * (kBlock / kWave) + w; t < nr; t += nw) {
         const uint32_t z = a.research_list[t];
         const int4 pz = a.pts[z];
@@ -577,7 +651,7 @@ __global__ void __launch_bounds__(kBlock) rb_research(RoundArrays a, GridView g)
         uint64_t d;
         int32_t id;
         const int L0 = start_level(g, z, K + 1, a.cell_alive);
-        wave_knn<K, kAlive>(g, z, pz, sc, K, L0, d, id, lds[w][0], lds[w][1]);
+        wave_knn<K, kAlive>(g, z, pz, sc, K, L0, d, id, lds[w][0], lds[w][1], &tested);
         const int c = __popcll(__ballot(lane < K && d != ~0ull));
         const int use = c < k ? c : k;
         const uint64_t wsum = wave_sum64(lane < use ? cost_term(d) : 0ull);
@@ -587,13 +661,12 @@ __global__ void __launch_bounds__(kBlock) rb_research(RoundArrays a, GridView g)
             if (a.check && wsum > a.cost[z]) st->err = 7;
             a.cost[z] = wsum;
         }
-        // reverse edges of the new members
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(&st->pool_count, (uint32_t)c);
-        base = (uint32_t)__shfl((int)base, 0, kWave);
+        // reverse edges of the new members, in pool nodes at fixed slots
+        // (K per re-search; rb_pool_end advances the pool past them)
         if (lane < c) {
-            const uint32_t node = base + (uint32_t)lane;
-            if (node < st->pool_cap) {
+            const uint64_t node64 = (uint64_t)pool_base + (uint64_t)t * K + (uint64_t)lane;
+            const uint32_t node = (uint32_t)node64;
+            if (node64 < st->pool_cap) {
                 a.pool_src[node] = (int32_t)z;
                 a.pool_next[node] = atomicExch(&a.head[id], (int32_t)node);
             } else {
@@ -601,7 +674,17 @@ __global__ void __launch_bounds__(kBlock) rb_research(RoundArrays a, GridView g)
             }
         }
     }
+    if (lane == 0 && tested) atomicAdd(&st->stat_rtested, (unsigned long long)tested);
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&st->stat_research, nr);
+}
+
+// Advances the reverse-list pool past the re-searches' nodes.
+__global__ void rb_pool_end(RoundArrays a) {
+    RoundDev* st = a.st;
+    if (st->done || st->err) return;
+    const uint64_t used = (uint64_t)st->pool_count + (uint64_t)st->nResearch * (uint64_t)a.K;
+    if (used > st->pool_cap) st->overflow = 1;
+    st->pool_count = (uint32_t)(used < st->pool_cap ? used : st->pool_cap);
 }
 
 __global__ void __launch_bounds__(kBlock) rb_compact(RoundArrays a, int par) {
@@ -610,7 +693,7 @@ __global__ void __launch_bounds__(kBlock) rb_compact(RoundArrays a, int par) {
     const uint32_t na = st->n_alive;
     const uint32_t* L = a.alive_list[par];
     uint32_t* M = a.alive_list[par ^ 1];
-    constexpr int IPT = 8;
+    constexpr int IPT = 32;  // items per thread: one shared-counter atomic per 8192 items
     for (uint32_t base = blockIdx.x * kBlock * IPT; base < na; base += gridDim.x * kBlock * IPT) {
         uint32_t item[IPT];
         uint32_t sel = 0, nsel = 0;
@@ -916,12 +999,14 @@ int segment_budgets(Ctx* c, RoundArrays& a) {
 
 template <int K>
 int launch_round(Ctx* c, RoundArrays& a, const GridView& g, const GridView& gs, int par) {
-    const unsigned G = 1024;
+    // per-item kernels take the configured launch size; the passes over
+    // all alive points a fixed one
+    const unsigned G = c->round_blocks, GS = 1024;
     hipLaunchKernelGGL(rb_begin, dim3(1), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_seg_reset, dim3(gfor(a.nseg)), dim3(kBlock), 0, c->stream, a);
-    hipLaunchKernelGGL(rb_hist0, dim3(G), dim3(kBlock), 0, c->stream, a, par);
+    hipLaunchKernelGGL(rb_hist0, dim3(GS), dim3(kBlock), 0, c->stream, a, par);
     hipLaunchKernelGGL(rb_find0, dim3(1), dim3(kBlock), 0, c->stream, a);
-    hipLaunchKernelGGL(rb_collect0, dim3(G), dim3(kBlock), 0, c->stream, a, par);
+    hipLaunchKernelGGL(rb_collect0, dim3(GS), dim3(kBlock), 0, c->stream, a, par);
     hipLaunchKernelGGL(rb_refine, dim3(1), dim3(1024), 0, c->stream, a);
     PDD_HIP(c, hipGetLastError());
     int rc;
@@ -930,10 +1015,10 @@ int launch_round(Ctx* c, RoundArrays& a, const GridView& g, const GridView& gs, 
     if (rc) return rc;
     hipLaunchKernelGGL(rb_remove, dim3(G), dim3(kBlock), 0, c->stream, a, g);
     hipLaunchKernelGGL(rb_remove_end, dim3(1), dim3(1), 0, c->stream, a);
-    hipLaunchKernelGGL(rb_touch, dim3(G), dim3(kBlock), 0, c->stream, a);
-    hipLaunchKernelGGL(rb_recost, dim3(G), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(rb_touch_recost, dim3(G), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_research<K>, dim3(G), dim3(kBlock), 0, c->stream, a, gs);
-    hipLaunchKernelGGL(rb_compact, dim3(G), dim3(kBlock), 0, c->stream, a, par);
+    hipLaunchKernelGGL(rb_pool_end, dim3(1), dim3(1), 0, c->stream, a);
+    hipLaunchKernelGGL(rb_compact, dim3(GS), dim3(kBlock), 0, c->stream, a, par);
     PDD_HIP(c, hipGetLastError());
     return PDD_OK;
 }
@@ -961,12 +1046,15 @@ int run_rounds(Ctx* c, RoundArrays& a, const GridView& g, uint32_t n) {
             c->stats[1] = hst->stat_research;
             c->stats[2] = hst->stat_danger;
             c->stats[7] = hst->stat_touch;
+            c->stats[12] = (int64_t)hst->stat_rtested;
+            c->stats[13] = (int64_t)hst->stat_enum;
             return PDD_OK;
         }
         if (c->progress && hst->round % 50 == 0) {
             fprintf(stderr, "pdd: round %u removed %u/%u alive %u A %u removed-now %u danger %u survivors %u "
-                    "researched %u enumerated %u frac %g\n", hst->round, hst->removed, hst->target, hst->n_alive_new, hst->nA, hst->nR,
-                    hst->nDanger, hst->nSurv, hst->nResearch, hst->work, hst->frac);
+                    "researched %u enumerated %u frac %g research-tested-total %llu\n", hst->round, hst->removed, hst->target,
+                    hst->n_alive_new, hst->nA, hst->nR, hst->nDanger, hst->nSurv, hst->nResearch, hst->work, hst->frac,
+                    hst->stat_rtested);
             fflush(stderr);
         }
         // rebuild the reverse lists when the appended chains overflowed or
@@ -1008,7 +1096,8 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, cons
     a.K = K;
     a.frac = frac;
     a.check = check;
-    const size_t pool_cap = (size_t)n * K;
+    // pool nodes are int32 indices; a full pool only triggers a rebuild
+    const size_t pool_cap = std::min<size_t>((size_t)n * K, (size_t)0x7FFFFFFF);
 #define ALLOC(field, slot, bytes)                                                         \
     do {                                                                                  \
         a.field = (std::remove_reference<decltype(a.field)>::type)scratch(c, slot, bytes); \
@@ -1031,7 +1120,6 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, cons
     ALLOC(dg_tc, kSDgC, (size_t)n * 8);
     ALLOC(dg_to, kSDgO, (size_t)n * 4);
     ALLOC(dg_dlast, kSDgD, (size_t)n * 8);
-    ALLOC(touch_list, kSTouch, (size_t)n * 4);
     ALLOC(research_list, kSResearch, (size_t)n * 4);
     ALLOC(R, kSR, (size_t)n * 4);
     ALLOC(ev_cost, kSEvC, (size_t)n * 8);

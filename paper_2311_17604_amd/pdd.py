@@ -19,7 +19,8 @@ PDD_F_PROGRESS = 4
 PHASES = ("grid", "knn", "reverse", "rounds", "final")
 
 STATS = ("rounds", "researches", "danger_checks", "reverse_rebuilds", "unused4", "voxel_log2",
-         "list_width", "touched", "knn_tested", "pred_hits", "pred_misses", "knn_fallbacks")
+         "list_width", "touched", "knn_tested", "pred_hits", "pred_misses", "knn_fallbacks",
+         "research_tested", "danger_enumerated")
 PRED_NPARAM = 8385
 
 _lib = None
@@ -34,7 +35,7 @@ class PddError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("b", ctypes.c_int32), ("voxel_log2", ctypes.c_int32),
                 ("round_frac", ctypes.c_float), ("point_stride", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("round_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 def load():
@@ -132,8 +133,8 @@ class Context:
         return {PHASES[i]: float(arr[i]) for i in range(n)}
 
     def stats(self) -> dict:
-        arr = (ctypes.c_int64 * 12)()
-        n = self.lib.pdd_last_stats(self.h, arr, 12)
+        arr = (ctypes.c_int64 * len(STATS))()
+        n = self.lib.pdd_last_stats(self.h, arr, len(STATS))
         return {STATS[i]: int(arr[i]) for i in range(n) if not STATS[i].startswith("unused")}
 
 
@@ -176,7 +177,7 @@ def grid_info(ctx: Context, xyz, voxel_log2: int = 0):
 
 def decimate(ctx: Context, xyz, keep: int, k: int, b: int = 0, voxel_log2: int = 0, round_frac: float = 0.0,
              check: bool = False, with_order: bool = True, out=None, timing: bool = False,
-             progress: bool = False):
+             progress: bool = False, round_blocks: int = 0):
     """Greedy decimation to `keep` points.  Returns (kept [keep] int32,
     order [n-keep] int32 or None, order_cost [n-keep] int64 (uint64 bits) or
     None).  `out` may supply preallocated (kept, order, order_cost)."""
@@ -191,7 +192,7 @@ def decimate(ctx: Context, xyz, keep: int, k: int, b: int = 0, voxel_log2: int =
         order_cost = torch.empty(n - keep, dtype=torch.int64, device=pts.device) if with_order else None
     o = Opts(k=k, b=b, voxel_log2=voxel_log2, round_frac=round_frac, point_stride=stride,
              flags=(PDD_F_CHECK if check else 0) | (PDD_F_TIMING if timing else 0)
-             | (PDD_F_PROGRESS if progress else 0))
+             | (PDD_F_PROGRESS if progress else 0), round_blocks=round_blocks)
     ctx._check(ctx.lib.pdd_decimate(ctx.h, _ptr(pts), n, keep, ctypes.byref(o), _ptr(kept), _ptr(order),
                                     _ptr(order_cost)), "pdd_decimate")
     return kept, order, order_cost
@@ -214,7 +215,7 @@ def autotune(ctx: Context, xyz, keep: int, k: int, sample: int = 0, b: int = 0, 
 
 def decimate_batch(ctx: Context, xyz, offsets, keeps, k: int, b: int = 0, voxel_log2: int = 0,
                    round_frac: float = 0.0, check: bool = False, with_order: bool = True, timing: bool = False,
-                   progress: bool = False):
+                   progress: bool = False, round_blocks: int = 0):
     """Independent clouds decimated together: cloud s is rows
     offsets[s]:offsets[s+1] of xyz and keeps keeps[s] points.  Returns
     (kept, order, order_cost), each the clouds' results one after another,
@@ -234,7 +235,7 @@ def decimate_batch(ctx: Context, xyz, offsets, keeps, k: int, b: int = 0, voxel_
     order_cost = torch.empty(m, dtype=torch.int64, device=pts.device) if with_order else None
     o = Opts(k=k, b=b, voxel_log2=voxel_log2, round_frac=round_frac, point_stride=stride,
              flags=(PDD_F_CHECK if check else 0) | (PDD_F_TIMING if timing else 0)
-             | (PDD_F_PROGRESS if progress else 0))
+             | (PDD_F_PROGRESS if progress else 0), round_blocks=round_blocks)
     ctx._check(ctx.lib.pdd_decimate_batch(ctx.h, _ptr(pts), off.ctypes.data_as(ctypes.c_void_p), nscan,
                                           kp.ctypes.data_as(ctypes.c_void_p), ctypes.byref(o), _ptr(kept),
                                           _ptr(order), _ptr(order_cost)), "pdd_decimate_batch")
