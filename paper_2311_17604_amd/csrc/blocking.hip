@@ -131,6 +131,11 @@ __global__ void __launch_bounds__(kBlock) rb_survive(RoundArrays a, GridView g) 
     if (st->done || st->err) return;
     const uint32_t nA = st->nA, round = st->round;
     const uint32_t n_it = (nA + blockDim.x - 1) / blockDim.x * blockDim.x;
+    uint64_t smin[kLev];
+#pragma unroll
+    for (int j = 0; j < kLev; j++) smin[j] = ~0ull;
+    uint32_t top_seg = kNone;
+    uint64_t top_cost = 0;
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_it; t += gridDim.x * blockDim.x) {
         bool sv = false;
         uint32_t x = 0;
@@ -172,40 +177,36 @@ __global__ void __launch_bounds__(kBlock) rb_survive(RoundArrays a, GridView g) 
                 atomicAdd(&a.cS[a.of0[x]], 1u);
             }
         }
-        const uint32_t p = wave_append(&st->nSurv, sv);
+        // the block's survivors: one shared-counter atomic per block
+        // (the loop bound is uniform over the block)
+        const uint32_t p = block_reserve(&st->nSurv, sv ? 1u : 0u);
         if (sv) a.surv_list[p] = x;
-        // lowest survivor cost per key level (wave minimum, one atomic per wave and level)
+        // lowest survivor cost per key level, kept per thread
 #pragma unroll
-        for (int j = 0; j < kLev; j++) {
-            uint64_t v = (sv && lev == j) ? cmax : ~0ull;
-#pragma unroll
-            for (int o = kWave / 2; o > 0; o >>= 1) {
-                const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o, kWave);
-                const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o, kWave);
-                const uint64_t u = ((uint64_t)hi << 32) | lo;
-                v = u < v ? u : v;
+        for (int j = 0; j < kLev; j++)
+            if (sv && lev == j && cmax < smin[j]) smin[j] = cmax;
+        // highest cost of each segment's A: kept per thread while the
+        // thread's points share one segment
+        if (act && cmax) {
+            const uint32_t sx = seg_of_pt(a, x);
+            if (top_seg == kNone || top_seg == sx) {
+                top_seg = sx;
+                if (cmax > top_cost) top_cost = cmax;
+            } else {
+                atomicMax((unsigned long long*)&a.seg_top_cost[sx], (unsigned long long)cmax);
             }
-            if ((threadIdx.x & (kWave - 1)) == 0 && v != ~0ull)
-                atomicMin((unsigned long long*)&st->surv_min[j], (unsigned long long)v);
-        }
-        // highest cost of each segment's A (wave maximum when the wave's A
-        // points share one segment, one atomic per wave)
-        const uint32_t sx = t < nA ? seg_of_pt(a, x) : 0u;
-        const uint32_t s0 = (uint32_t)__shfl((int)sx, 0, kWave);
-        if (__all(t >= nA || sx == s0)) {
-#pragma unroll
-            for (int o = kWave / 2; o > 0; o >>= 1) {
-                const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)cmax, o, kWave);
-                const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(cmax >> 32), o, kWave);
-                const uint64_t v = ((uint64_t)hi << 32) | lo;
-                cmax = v > cmax ? v : cmax;
-            }
-            if ((threadIdx.x & (kWave - 1)) == 0 && cmax)
-                atomicMax((unsigned long long*)&a.seg_top_cost[s0], (unsigned long long)cmax);
-        } else if (t < nA && cmax) {
-            atomicMax((unsigned long long*)&a.seg_top_cost[sx], (unsigned long long)cmax);
         }
     }
+    // block minima / maxima: one atomic per block (and level)
+    __shared__ unsigned long long s_min[kLev];
+    if (threadIdx.x < kLev) s_min[threadIdx.x] = ~0ull;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kLev; j++)
+        if (smin[j] != ~0ull) atomicMin(&s_min[j], (unsigned long long)smin[j]);
+    block_seg_max64(a.seg_top_cost, top_seg, top_cost);
+    if (threadIdx.x < kLev && s_min[threadIdx.x] != ~0ull)
+        atomicMin((unsigned long long*)&st->surv_min[threadIdx.x], s_min[threadIdx.x]);
 }
 
 // Groups the survivors by level-0 cell (offsets from the scan of cS), so

@@ -94,6 +94,47 @@ __device__ inline uint32_t wave_append(uint32_t* counter, bool pred) {
     return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
 }
 
+// arr[seg] -= cnt for every thread with cnt > 0; the threads of the block
+// that share the first such thread's seg add up in LDS and make one global
+// atomic.  Every thread of the block must call it.
+__device__ inline void block_seg_sub(uint32_t* arr, uint32_t seg, uint32_t cnt) {
+    __shared__ uint32_t s_seg, s_sum;
+    if (threadIdx.x == 0) {
+        s_seg = 0xFFFFFFFFu;
+        s_sum = 0;
+    }
+    __syncthreads();
+    if (cnt) atomicCAS(&s_seg, 0xFFFFFFFFu, seg);
+    __syncthreads();
+    if (cnt) {
+        if (s_seg == seg) atomicAdd(&s_sum, cnt);
+        else atomicSub(&arr[seg], cnt);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_sum) atomicSub(&arr[s_seg], s_sum);
+}
+
+// arr[seg] = max(arr[seg], v) for every thread with seg != 0xFFFFFFFF, in
+// the same way (one global atomic for the block's first segment).
+__device__ inline void block_seg_max64(uint64_t* arr, uint32_t seg, uint64_t v) {
+    __shared__ uint32_t s_seg;
+    __shared__ unsigned long long s_max;
+    if (threadIdx.x == 0) {
+        s_seg = 0xFFFFFFFFu;
+        s_max = 0;
+    }
+    __syncthreads();
+    const bool has = seg != 0xFFFFFFFFu;
+    if (has) atomicCAS(&s_seg, 0xFFFFFFFFu, seg);
+    __syncthreads();
+    if (has) {
+        if (s_seg == seg) atomicMax(&s_max, (unsigned long long)v);
+        else atomicMax((unsigned long long*)&arr[seg], (unsigned long long)v);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_max) atomicMax((unsigned long long*)&arr[s_seg], s_max);
+}
+
 // Space for `cnt` items per thread of a kBlock-thread block: returns the
 // thread's first slot; one atomic on `counter` per block.  Every thread of
 // the block must call it.

@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(kBlock) rb_collect0(RoundArrays a, int par) {
     if (st->done || st->err) return;
     const uint32_t na = st->n_alive, bsel = st->sel_bin, round = st->round, mode = st->mode;
     const uint32_t* L = a.alive_list[par];
-    constexpr int IPT = 32;  // items per thread: one shared-counter atomic per 8192 items
+    constexpr int IPT = 8;
     for (uint32_t base = blockIdx.x * kBlock * IPT; base < na; base += gridDim.x * kBlock * IPT) {
         uint32_t item[IPT];
         uint32_t selA = 0, selC = 0, nA = 0, nC = 0;
@@ -435,6 +435,7 @@ __global__ void __launch_bounds__(kBlock) rb_remove(RoundArrays a, GridView g) {
     if (st->done || st->err) return;
     const uint32_t nA = st->nA, round = st->round;
     const uint32_t n_it = (nA + blockDim.x - 1) / blockDim.x * blockDim.x;
+    uint32_t run_seg = 0, run_cnt = 0;  // removals of the thread's current segment
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_it; t += gridDim.x * blockDim.x) {
         uint32_t x = 0;
         bool rm = false;
@@ -479,15 +480,24 @@ __global__ void __launch_bounds__(kBlock) rb_remove(RoundArrays a, GridView g) {
                 if (act && L + 1 < g.nlev) c = g.lv[L].parent[c];
             }
         }
-        const uint32_t p = wave_append(&st->nR, rm);
+        // one shared-counter atomic per block (the loop bound is uniform over
+        // the block)
+        const uint32_t p = block_reserve(&st->nR, rm ? 1u : 0u);
         if (rm) {
             a.R[p] = x;
             a.ev_cost[st->removed + p] = a.cost[x];
             a.ev_orig[st->removed + p] = a.pts[x].w;
             a.alive[x] = 0;
-            atomicSub(&a.seg_left[seg_of_pt(a, x)], 1u);
+            const uint32_t sx = seg_of_pt(a, x);
+            if (run_cnt && sx != run_seg) {
+                atomicSub(&a.seg_left[run_seg], run_cnt);
+                run_cnt = 0;
+            }
+            run_seg = sx;
+            run_cnt++;
         }
     }
+    block_seg_sub(a.seg_left, run_seg, run_cnt);
 }
 
 __global__ void rb_remove_end(RoundArrays a) {
@@ -506,46 +516,47 @@ __global__ void rb_remove_end(RoundArrays a) {
 }
 
 // Re-costs every alive point whose list held a removed point (the removed
-// points' reverse lists): one wavefront per 64 removed points.  Points
-// touched first by this wave are staged in its LDS and re-costed 64 at a
-// time, one per lane, from their lists' first k alive entries; a list with
-// fewer alive entries than k that did not hold every alive point is queued
-// for the re-search (staged as well: one shared-counter atomic per 64).
+// points' reverse lists): one wavefront per removed point, one lane per
+// reverse entry.  The lane that touches a point first this round re-costs
+// it from its list's first k alive entries; a list with fewer alive entries
+// than k that did not hold every alive point is queued for the re-search
+// (staged in the wave's LDS: one shared-counter atomic per 64 entries).
 __global__ void __launch_bounds__(kBlock) rb_touch_recost(RoundArrays a) {
     RoundDev* st = a.st;
     if (st->done || st->err) return;
     constexpr int W = kBlock / kWave;
-    __shared__ uint32_t s_touch[W][2 * kWave], s_rs[W][2 * kWave], s_cnt[W];
+    __shared__ uint32_t s_rs[W][2 * kWave], s_chain[W][kWave], s_cnt[W];
     const uint32_t nR = st->nR, round = st->round;
     const int K = a.K, k = a.k;
     const int lane = (int)lane_id(), w = threadIdx.x / kWave;
     const uint64_t below = (1ull << lane) - 1ull;
-    uint32_t nt = 0, nrs = 0, ntouched = 0;  // wave-uniform
-    // re-cost s_touch[w][0, m)
-    auto recost = [&](uint32_t m) {
+    uint32_t nrs = 0, ntouched = 0;  // wave-uniform
+    // touch z (if valid) and re-cost it when this lane touched it first;
+    // every lane of the wave calls it
+    auto visit = [&](bool valid, uint32_t z) {
+        const bool fresh = valid && a.alive[z] && atomicExch(&a.touched[z], round) != round;
         bool rs = false;
-        uint32_t z = 0;
-        if ((uint32_t)lane < m) {
-            z = s_touch[w][lane];
+        if (fresh) {
             const int4 pz = a.pts[z];
             const int c = a.cnt[z];
             const int32_t* nb = a.nbr + (size_t)z * K;
-            int valid = 0;
+            int nvalid = 0;
             uint64_t wsum = 0;
-            for (int j = 0; j < c && valid < k; j++) {
+            for (int j = 0; j < c && nvalid < k; j++) {
                 const uint32_t y = (uint32_t)nb[j];
                 if (!a.alive[y]) continue;
                 const int4 py = a.pts[y];
                 wsum += cost_term(dist2(pz.x, pz.y, pz.z, py.x, py.y, py.z));
-                valid++;
+                nvalid++;
             }
-            if (valid < k && c == K) {
+            if (nvalid < k && c == K) {
                 rs = true;
             } else {
                 if (a.check && wsum > a.cost[z]) st->err = 6;
                 a.cost[z] = wsum;
             }
         }
+        ntouched += (uint32_t)__popcll(__ballot(fresh));
         const uint64_t bm = __ballot(rs);
         if (rs) s_rs[w][nrs + (uint32_t)__popcll(bm & below)] = z;
         nrs += (uint32_t)__popcll(bm);
@@ -563,56 +574,33 @@ __global__ void __launch_bounds__(kBlock) rb_touch_recost(RoundArrays a) {
             wave_sync_lds();
         }
     };
-    // stage the lanes' newly touched points; re-cost once 64 are waiting
-    auto stage = [&](bool fresh, uint32_t z) {
-        const uint64_t m = __ballot(fresh);
-        if (fresh) s_touch[w][nt + (uint32_t)__popcll(m & below)] = z;
-        nt += (uint32_t)__popcll(m);
-        ntouched += (uint32_t)__popcll(m);
-        wave_sync_lds();
-        if (nt >= (uint32_t)kWave) {
-            recost(kWave);
-            const uint32_t rem = nt - kWave;
-            const uint32_t v = (uint32_t)lane < rem ? s_touch[w][kWave + lane] : 0u;
-            wave_sync_lds();
-            if ((uint32_t)lane < rem) s_touch[w][lane] = v;
-            nt = rem;
-            wave_sync_lds();
+    const uint32_t nw = gridDim.x * W;
+    for (uint32_t t = blockIdx.x * W + w; t < nR; t += nw) {
+        const uint32_t x = a.R[t];
+        // the CSR part, 64 entries at a time
+        const uint32_t e0 = a.rev_off[x], e1 = a.rev_off[x + 1];
+        for (uint32_t e = e0; e < e1; e += kWave) {
+            const bool valid = e + (uint32_t)lane < e1;
+            visit(valid, valid ? (uint32_t)a.rev_src[e + lane] : 0u);
         }
-    };
-    const uint32_t stride = gridDim.x * W * kWave;
-    for (uint32_t base = (blockIdx.x * W + w) * kWave; base < nR; base += stride) {
-        const uint32_t t = base + (uint32_t)lane;
-        uint32_t e = 0, e1 = 0;
-        int32_t p = -1;
-        if (t < nR) {
-            const uint32_t x = a.R[t];
-            e = a.rev_off[x];
-            e1 = a.rev_off[x + 1];
-            p = a.head[x];
-        }
-        // reverse entries in the CSR part, then in the appended chains
-        while (__ballot(e < e1)) {
-            bool fresh = false;
-            uint32_t z = 0;
-            if (e < e1) {
-                z = (uint32_t)a.rev_src[e++];
-                fresh = a.alive[z] && atomicExch(&a.touched[z], round) != round;
+        // the appended chain: lane 0 walks up to 64 nodes, the lanes visit them
+        int32_t p = a.head[x];
+        while (p >= 0) {
+            uint32_t m = 0;
+            if (lane == 0) {
+                while (p >= 0 && m < (uint32_t)kWave) {
+                    s_chain[w][m++] = (uint32_t)a.pool_src[p];
+                    p = a.pool_next[p];
+                }
             }
-            stage(fresh, z);
-        }
-        while (__ballot(p >= 0)) {
-            bool fresh = false;
-            uint32_t z = 0;
-            if (p >= 0) {
-                z = (uint32_t)a.pool_src[p];
-                p = a.pool_next[p];
-                fresh = a.alive[z] && atomicExch(&a.touched[z], round) != round;
-            }
-            stage(fresh, z);
+            m = (uint32_t)__shfl((int)m, 0, kWave);
+            p = __shfl(p, 0, kWave);
+            wave_sync_lds();
+            const bool valid = (uint32_t)lane < m;
+            visit(valid, valid ? s_chain[w][lane] : 0u);
+            wave_sync_lds();
         }
     }
-    if (nt) recost(nt);
     if (nrs) {
         uint32_t base = 0;
         if (lane == 0) base = atomicAdd(&st->nResearch, nrs);
@@ -693,7 +681,7 @@ __global__ void __launch_bounds__(kBlock) rb_compact(RoundArrays a, int par) {
     const uint32_t na = st->n_alive;
     const uint32_t* L = a.alive_list[par];
     uint32_t* M = a.alive_list[par ^ 1];
-    constexpr int IPT = 32;  // items per thread: one shared-counter atomic per 8192 items
+    constexpr int IPT = 8;
     for (uint32_t base = blockIdx.x * kBlock * IPT; base < na; base += gridDim.x * kBlock * IPT) {
         uint32_t item[IPT];
         uint32_t sel = 0, nsel = 0;
