@@ -24,6 +24,15 @@ struct RoundDev {
     float frac_max;
     uint32_t work;                // survivors enumerated by the danger checks, this round
     uint32_t pad3;
+    // candidate pool: every alive point outside it has bin0(cost) < p_lo, so
+    // its members with bin0(cost) >= p_lo are an upper set of the keys
+    uint32_t n_list;              // entries of the alive list (dead ones included)
+    uint32_t n_list_new;          // its length after this round's compaction (full rounds)
+    uint32_t apar;                // which alive-list buffer is current
+    uint32_t full;                // this round ranks all alive points (and rebuilds the pool)
+    uint32_t pcur, nP, nP_next;   // current pool buffer and its length; length after compaction
+    uint32_t p_lo, p_valid;
+    uint32_t pad4;
     unsigned long long stat_rtested;  // points looked at by the re-searches, all rounds
     unsigned long long stat_enum;     // survivors enumerated by the danger checks, all rounds
     uint64_t surv_min[kLev];      // lowest survivor cost per key level, this round
@@ -41,6 +50,7 @@ struct RoundArrays {
     uint32_t* touched;
     uint32_t* surv;
     uint32_t* alive_list[2];
+    uint32_t* pool_list[2];  // candidate pool (see RoundDev)
     uint32_t* A;
     uint32_t* cand[2];
     uint32_t* dg_y;      // danger list

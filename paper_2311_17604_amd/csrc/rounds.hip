@@ -57,6 +57,9 @@ __device__ inline uint32_t key_digit(uint64_t c, int32_t orig, int lo, int w) {
 // selection of A
 // ---------------------------------------------------------------------------
 
+// candidate pool size: kPoolFactor * m points (at least kPoolMin) when built
+constexpr uint32_t kPoolFactor = 8, kPoolMin = 1u << 16;
+
 __global__ void rb_begin(RoundArrays a) {
     RoundDev* st = a.st;
     __shared__ int skip;
@@ -66,7 +69,6 @@ __global__ void rb_begin(RoundArrays a) {
             skip = 1;
         } else {
             if (st->round > 0) st->n_alive = st->n_alive_new;
-            st->n_alive_new = 0;
             if (st->removed >= st->target) {
                 st->done = 1;
                 skip = 1;
@@ -81,6 +83,9 @@ __global__ void rb_begin(RoundArrays a) {
                 st->nOvf = 0;
                 st->work = 0;
                 for (int j = 0; j < kLev; j++) st->surv_min[j] = ~0ull;
+                st->full = st->p_valid ? 0u : 1u;
+                st->nP_next = 0;
+                st->n_list_new = 0;
             }
         }
     }
@@ -89,22 +94,90 @@ __global__ void rb_begin(RoundArrays a) {
     for (int i = threadIdx.x; i < kSelBins0; i += blockDim.x) a.hist[i] = 0;
 }
 
-__global__ void __launch_bounds__(kBlock) rb_hist0(RoundArrays a, int par) {
-    const RoundDev* st = a.st;
+// Key histogram of the ranked points: in a full round every alive point
+// (the alive list still holds points removed since its last compaction), in
+// a pool round the pool members with bin0(cost) >= p_lo, which this pass
+// also compacts into the other pool buffer.  st->full: 0 pool round, 1 full
+// round, 2 full round decided by rb_pool_check after the pool pass; pass 0
+// runs before that check, pass 1 after it (full rounds of kind 2 only).
+__global__ void __launch_bounds__(kBlock) rb_hist0(RoundArrays a, int pass) {
+    RoundDev* st = a.st;
     if (st->done || st->err) return;
+    if (pass == 1 && st->full != 2) return;
     __shared__ uint32_t h[kSelBins0];
     for (int i = threadIdx.x; i < kSelBins0; i += blockDim.x) h[i] = 0;
     __syncthreads();
-    const uint32_t na = st->n_alive;
-    const uint32_t* L = a.alive_list[par];
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < na; t += gridDim.x * blockDim.x) {
-        const uint32_t x = L[t];
-        if (a.seg && a.seg_left[a.seg[x]] == 0) continue;  // segment done: not ranked
-        atomicAdd(&h[bin0(a.cost[x])], 1u);
+    if (st->full) {
+        const uint32_t na = st->n_list;
+        const uint32_t* L = a.alive_list[st->apar];
+        for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < na; t += gridDim.x * blockDim.x) {
+            const uint32_t x = L[t];
+            if (!a.alive[x]) continue;
+            if (a.seg && a.seg_left[a.seg[x]] == 0) continue;  // segment done: not ranked
+            atomicAdd(&h[bin0(a.cost[x])], 1u);
+        }
+    } else {
+        const uint32_t np = st->nP, lo = st->p_lo;
+        const uint32_t* P = a.pool_list[st->pcur];
+        uint32_t* Q = a.pool_list[st->pcur ^ 1u];
+        constexpr int IPT = 8;
+        for (uint32_t base = blockIdx.x * kBlock * IPT; base < np; base += gridDim.x * kBlock * IPT) {
+            uint32_t item[IPT];
+            uint32_t sel = 0, nsel = 0;
+#pragma unroll
+            for (int e = 0; e < IPT; e++) {
+                const uint32_t t = base + e * kBlock + threadIdx.x;
+                item[e] = 0;
+                if (t < np) {
+                    const uint32_t x = P[t];
+                    item[e] = x;
+                    if (a.alive[x] && !(a.seg && a.seg_left[a.seg[x]] == 0)) {
+                        const uint32_t bb = bin0(a.cost[x]);
+                        if (bb >= lo) {
+                            atomicAdd(&h[bb], 1u);
+                            sel |= 1u << e;
+                            nsel++;
+                        }
+                    }
+                }
+            }
+            uint32_t p = block_reserve(&st->nP_next, nsel);
+#pragma unroll
+            for (int e = 0; e < IPT; e++)
+                if ((sel >> e) & 1u) Q[p++] = item[e];
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kSelBins0; i += blockDim.x)
         if (h[i]) atomicAdd(&a.hist[i], h[i]);
+}
+
+// Pool round: the compacted pool becomes current when it holds at least half
+// of m (it is an upper set, so its top is the top of all alive points);
+// otherwise the round is a full one.
+__global__ void rb_pool_check(RoundArrays a) {
+    RoundDev* st = a.st;
+    if (st->done || st->err || st->full) return;
+    __shared__ uint32_t total;
+    if (threadIdx.x == 0) total = 0;
+    __syncthreads();
+    uint32_t part = 0;
+    for (int i = threadIdx.x; i < kSelBins0; i += blockDim.x) part += a.hist[i];
+    atomicAdd(&total, part);
+    __syncthreads();
+    const bool full = 2ull * total < (uint64_t)st->m;
+    if (full) {
+        for (int i = threadIdx.x; i < kSelBins0; i += blockDim.x) a.hist[i] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (full) {
+            st->full = 2;
+        } else {
+            st->pcur ^= 1u;
+            st->nP = st->nP_next;
+        }
+    }
 }
 
 // Bin holding the `need`-th largest key (bins counted from the top) and how
@@ -159,6 +232,17 @@ __global__ void __launch_bounds__(kBlock) rb_find0(RoundArrays a) {
     if (threadIdx.x == 0 && total < st->m) st->m = total > 0 ? total : 1u;
     __syncthreads();
     find_bin(a.hist, kSelBins0, st->m, &b, &need);
+    if (st->full) {
+        // the new pool: the bins from the one holding the M-th largest key up
+        __shared__ uint32_t pb, pneed;
+        const uint64_t want = std::max<uint64_t>((uint64_t)kPoolFactor * st->m, (uint64_t)kPoolMin);
+        const uint32_t M = (uint32_t)std::min<uint64_t>(want, (uint64_t)total);
+        find_bin(a.hist, kSelBins0, M, &pb, &pneed);
+        if (threadIdx.x == 0) {
+            st->p_lo = pb;
+            st->nP = 0;
+        }
+    }
     if (threadIdx.x == 0) {
         st->sel_bin = b;
         // A = the bins above b, plus (mode 1) the exact top `need` of bin b
@@ -190,24 +274,43 @@ __global__ void __launch_bounds__(kBlock) rb_find0(RoundArrays a) {
     }
 }
 
-__global__ void __launch_bounds__(kBlock) rb_collect0(RoundArrays a, int par) {
+// A (bins above sel_bin) and, in mode 1, the candidates of bin sel_bin.  A
+// full round collects them from the alive list, which it compacts, and
+// builds the pool (bins >= p_lo); a pool round collects them from the pool
+// that rb_hist0 compacted.
+__global__ void __launch_bounds__(kBlock) rb_collect0(RoundArrays a) {
     RoundDev* st = a.st;
     if (st->done || st->err) return;
-    const uint32_t na = st->n_alive, bsel = st->sel_bin, round = st->round, mode = st->mode;
-    const uint32_t* L = a.alive_list[par];
+    const uint32_t bsel = st->sel_bin, round = st->round, mode = st->mode, full = st->full, lo = st->p_lo;
+    const uint32_t na = full ? st->n_list : st->nP;
+    const uint32_t* L = full ? a.alive_list[st->apar] : a.pool_list[st->pcur];
+    uint32_t* Lc = a.alive_list[st->apar ^ 1u];
+    uint32_t* P = a.pool_list[st->pcur];
     constexpr int IPT = 8;
     for (uint32_t base = blockIdx.x * kBlock * IPT; base < na; base += gridDim.x * kBlock * IPT) {
         uint32_t item[IPT];
-        uint32_t selA = 0, selC = 0, nA = 0, nC = 0;
+        uint32_t selA = 0, selC = 0, selL = 0, selP = 0, nA = 0, nC = 0, nL = 0, nP = 0;
 #pragma unroll
         for (int e = 0; e < IPT; e++) {
             const uint32_t t = base + e * kBlock + threadIdx.x;
             item[e] = 0;
             if (t < na) {
                 const uint32_t i = L[t];
-                const bool elig = !(a.seg && a.seg_left[a.seg[i]] == 0);  // segment done: not ranked
-                const uint32_t bb = elig ? bin0(a.cost[i]) : 0u;
                 item[e] = i;
+                bool elig = true;
+                if (full) {
+                    const bool al = a.alive[i] != 0;
+                    if (al) {
+                        selL |= 1u << e;
+                        nL++;
+                    }
+                    elig = al && !(a.seg && a.seg_left[a.seg[i]] == 0);  // segment done: not ranked
+                }
+                const uint32_t bb = elig ? bin0(a.cost[i]) : 0u;
+                if (full && elig && bb >= lo) {
+                    selP |= 1u << e;
+                    nP++;
+                }
                 if (elig && bb > bsel) {
                     selA |= 1u << e;
                     nA++;
@@ -219,6 +322,8 @@ __global__ void __launch_bounds__(kBlock) rb_collect0(RoundArrays a, int par) {
         }
         uint32_t pA = block_reserve(&st->nA, nA);
         uint32_t pC = mode == 1 ? block_reserve(&st->nCand, nC) : 0u;
+        uint32_t pL = full ? block_reserve(&st->n_list_new, nL) : 0u;
+        uint32_t pP = full ? block_reserve(&st->nP, nP) : 0u;
 #pragma unroll
         for (int e = 0; e < IPT; e++) {
             if ((selA >> e) & 1u) {
@@ -227,6 +332,8 @@ __global__ void __launch_bounds__(kBlock) rb_collect0(RoundArrays a, int par) {
             } else if ((selC >> e) & 1u) {
                 a.cand[0][pC++] = item[e];
             }
+            if ((selL >> e) & 1u) Lc[pL++] = item[e];
+            if ((selP >> e) & 1u) P[pP++] = item[e];
         }
     }
 }
@@ -505,6 +612,13 @@ __global__ void rb_remove_end(RoundArrays a) {
     if (st->done || st->err) return;
     if (st->nR == 0) st->err = 5;  // the top key is never blocked
     st->removed += st->nR;
+    st->n_alive_new = st->n_alive - st->nR;
+    if (st->full) {
+        // the compacted alive list and the new pool take over
+        st->apar ^= 1u;
+        st->n_list = st->n_list_new;
+        st->p_valid = 1;
+    }
     st->stat_surv += st->nSurv;
     // adapt the ranked share: a round that frees few of A (a dense region
     // filling A), or whose danger checks enumerate many survivors (their
@@ -675,34 +789,6 @@ __global__ void rb_pool_end(RoundArrays a) {
     st->pool_count = (uint32_t)(used < st->pool_cap ? used : st->pool_cap);
 }
 
-__global__ void __launch_bounds__(kBlock) rb_compact(RoundArrays a, int par) {
-    RoundDev* st = a.st;
-    if (st->done || st->err) return;
-    const uint32_t na = st->n_alive;
-    const uint32_t* L = a.alive_list[par];
-    uint32_t* M = a.alive_list[par ^ 1];
-    constexpr int IPT = 8;
-    for (uint32_t base = blockIdx.x * kBlock * IPT; base < na; base += gridDim.x * kBlock * IPT) {
-        uint32_t item[IPT];
-        uint32_t sel = 0, nsel = 0;
-#pragma unroll
-        for (int e = 0; e < IPT; e++) {
-            const uint32_t t = base + e * kBlock + threadIdx.x;
-            item[e] = 0;
-            if (t < na) {
-                item[e] = L[t];
-                if (a.alive[item[e]]) {
-                    sel |= 1u << e;
-                    nsel++;
-                }
-            }
-        }
-        uint32_t p = block_reserve(&st->n_alive_new, nsel);
-#pragma unroll
-        for (int e = 0; e < IPT; e++)
-            if ((sel >> e) & 1u) M[p++] = item[e];
-    }
-}
 
 // ---------------------------------------------------------------------------
 // reverse lists
@@ -739,6 +825,8 @@ __global__ void rev_reset_k(RoundArrays a) {
 __global__ void rd_init(RoundDev* st, uint32_t n, uint32_t target, uint32_t pool_cap, float frac) {
     RoundDev z = {};
     z.n_alive = n;
+    z.n_alive_new = n;
+    z.n_list = n;
     z.target = target;
     z.pool_cap = pool_cap;
     z.frac = frac;
@@ -896,7 +984,8 @@ enum {
     kSFin1, kSFin2, kSSurv,
     kSCellAlive = 60, kSCellA, kSDgC, kSDgO, kSDgD, kSSurvOff, kSSurvList, kSSurvBucket, kSCS, kSGrpLo, kSGrpHi,
     kSGSafe, kSAPts, kSAStart, kSAFlag, kSAPos,
-    kSOvfK0 = 89, kSOvfV0, kSOvfK1, kSOvfV1, kSSegFirst, kSSeg, kSOff, kSSegCnt, kSSegGlob, kSSegTopC, kSSegTopO
+    kSOvfK0 = 89, kSOvfV0, kSOvfK1, kSOvfV1, kSSegFirst, kSSeg, kSOff, kSSegCnt, kSSegGlob, kSSegTopC, kSSegTopO,
+    kSPool0 = 101, kSPool1
 };
 static_assert(kSSurv < 40, "scratch slots overlap the scan's");
 static_assert(kSAPos < 76 && kSSegTopO < kScratchSlots, "scratch slots beyond the context's table");
@@ -986,15 +1075,17 @@ int segment_budgets(Ctx* c, RoundArrays& a) {
 }
 
 template <int K>
-int launch_round(Ctx* c, RoundArrays& a, const GridView& g, const GridView& gs, int par) {
+int launch_round(Ctx* c, RoundArrays& a, const GridView& g, const GridView& gs) {
     // per-item kernels take the configured launch size; the passes over
-    // all alive points a fixed one
+    // the alive points or the pool a fixed one
     const unsigned G = c->round_blocks, GS = 1024;
     hipLaunchKernelGGL(rb_begin, dim3(1), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_seg_reset, dim3(gfor(a.nseg)), dim3(kBlock), 0, c->stream, a);
-    hipLaunchKernelGGL(rb_hist0, dim3(GS), dim3(kBlock), 0, c->stream, a, par);
+    hipLaunchKernelGGL(rb_hist0, dim3(GS), dim3(kBlock), 0, c->stream, a, 0);
+    hipLaunchKernelGGL(rb_pool_check, dim3(1), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(rb_hist0, dim3(GS), dim3(kBlock), 0, c->stream, a, 1);
     hipLaunchKernelGGL(rb_find0, dim3(1), dim3(kBlock), 0, c->stream, a);
-    hipLaunchKernelGGL(rb_collect0, dim3(GS), dim3(kBlock), 0, c->stream, a, par);
+    hipLaunchKernelGGL(rb_collect0, dim3(GS), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_refine, dim3(1), dim3(1024), 0, c->stream, a);
     PDD_HIP(c, hipGetLastError());
     int rc;
@@ -1006,7 +1097,6 @@ int launch_round(Ctx* c, RoundArrays& a, const GridView& g, const GridView& gs, 
     hipLaunchKernelGGL(rb_touch_recost, dim3(G), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_research<K>, dim3(G), dim3(kBlock), 0, c->stream, a, gs);
     hipLaunchKernelGGL(rb_pool_end, dim3(1), dim3(1), 0, c->stream, a);
-    hipLaunchKernelGGL(rb_compact, dim3(GS), dim3(kBlock), 0, c->stream, a, par);
     PDD_HIP(c, hipGetLastError());
     return PDD_OK;
 }
@@ -1014,15 +1104,13 @@ int launch_round(Ctx* c, RoundArrays& a, const GridView& g, const GridView& gs, 
 template <int K>
 int run_rounds(Ctx* c, RoundArrays& a, const GridView& g, uint32_t n) {
     RoundDev* hst = (RoundDev*)c->pinned;
-    int par = 0;
     GridView gs;
     int rc = build_alive_view(c, a, g, &gs);
     if (rc) return rc;
     uint32_t view_alive = n;
     for (uint64_t it = 0;; it++) {
-        rc = launch_round<K>(c, a, g, gs, par);
+        rc = launch_round<K>(c, a, g, gs);
         if (rc) return rc;
-        par ^= 1;
         PDD_HIP(c, hipMemcpyAsync(hst, a.st, sizeof(RoundDev), hipMemcpyDeviceToHost, c->stream));
         PDD_HIP(c, hipStreamSynchronize(c->stream));
         if (hst->err) {
@@ -1101,6 +1189,8 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, cons
     ALLOC(surv, kSSurv, (size_t)n * 4);
     ALLOC(alive_list[0], kSAl0, (size_t)n * 4);
     ALLOC(alive_list[1], kSAl1, (size_t)n * 4);
+    ALLOC(pool_list[0], kSPool0, (size_t)n * 4);
+    ALLOC(pool_list[1], kSPool1, (size_t)n * 4);
     ALLOC(A, kSA, (size_t)n * 4);
     ALLOC(cand[0], kSC0, (size_t)n * 4);
     ALLOC(cand[1], kSC1, (size_t)n * 4);
