@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(kBlock) rb_survive(RoundArrays a, GridView g) 
             uint32_t c = act ? a.of0[x] : 0u;
             const uint64_t am = __ballot(act);
             const int leader = am ? __ffsll((unsigned long long)am) - 1 : 0;
-            for (int L = 0; L < g.nlev && am; L++) {
+            for (int L = 0; L < a.lc && am; L++) {
                 const uint32_t gc = g.lv[L].base + c;
                 const uint32_t g0 = (uint32_t)__shfl((int)gc, leader, kWave);
                 if (__all(!act || gc == g0)) {
@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(kBlock) rb_survive(RoundArrays a, GridView g) 
                 } else if (act) {
                     atomicAdd(&a.cellAlev[(size_t)gc * kLev + lev], 1u);
                 }
-                if (act && L + 1 < g.nlev) c = g.lv[L].parent[c];
+                if (act && L + 1 < a.lc) c = g.lv[L].parent[c];
             }
         }
         if (act) {
@@ -498,6 +498,7 @@ int launch_k(Ctx* c, const RoundArrays& a, const GridView& g) {
     hipLaunchKernelGGL(rb_group, dim3(G), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_pair<K>, dim3(G), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_survive, dim3(G), dim3(kBlock), 0, c->stream, a, g);
+    launch_coarse(c, a, g, 0);
     PDD_HIP(c, hipGetLastError());
     int rc = exclusive_scan_u32(c, a.cS, a.surv_off, a.ncells0 + 1, nullptr);
     if (rc) return rc;

@@ -69,6 +69,11 @@ struct RoundArrays {
     int32_t* pool_next;
     uint32_t* cell_alive;   // [total cells] alive points per cell, all levels (index base + cell)
     uint32_t* cellAlev;     // [total cells * kLev] A points per cell and key level, this round
+    // Levels >= lc (few, large cells) are not updated point by point, which
+    // would make many waves add to the same counters; rb_coarse recomputes
+    // them from their children (clo: first child of each cell, by global id)
+    int lc;
+    uint32_t* clo;
     uint32_t* surv_list;    // [n] survivors of this round
     const uint32_t* grp_lo; // [n] run of points with identical coordinates around each
     const uint32_t* grp_hi; //     point in Morton order: [grp_lo, grp_hi)
@@ -191,6 +196,11 @@ __device__ inline int level_of(const RoundDev* st, uint64_t cost) {
     for (int j = 1; j < kLev; j++) l += b >= st->lev_t[j];
     return l;
 }
+
+// Per-cell counts of the levels >= a.lc from the level below, level by
+// level, in one block: A points per key level (what = 0) or alive points
+// (what = 1).  Children of a cell are a run of the level below (Morton order).
+void launch_coarse(Ctx* c, const RoundArrays& a, const GridView& g, int what);
 
 // blocking kernels (blocking.hip), enqueued on the context's stream
 int launch_blocking(Ctx* c, const RoundArrays& a, const GridView& g, int K);

@@ -570,7 +570,7 @@ __global__ void __launch_bounds__(kBlock) rb_remove(RoundArrays a, GridView g) {
             const uint64_t am = __ballot(act);
             const int leader = am ? __ffsll((unsigned long long)am) - 1 : 0;
             const int lane = (int)(threadIdx.x & (kWave - 1));
-            for (int L = 0; L < g.nlev && am; L++) {
+            for (int L = 0; L < a.lc && am; L++) {
                 const uint32_t gc = g.lv[L].base + c;
                 const uint32_t g0 = (uint32_t)__shfl((int)gc, leader, kWave);
                 const bool uni = __all(!act || gc == g0);
@@ -584,7 +584,7 @@ __global__ void __launch_bounds__(kBlock) rb_remove(RoundArrays a, GridView g) {
                 } else if (rm) {
                     atomicSub(&a.cell_alive[gc], 1u);
                 }
-                if (act && L + 1 < g.nlev) c = g.lv[L].parent[c];
+                if (act && L + 1 < a.lc) c = g.lv[L].parent[c];
             }
         }
         // one shared-counter atomic per block (the loop bound is uniform over
@@ -778,6 +778,38 @@ __global__ void __launch_bounds__(kBlock) rb_research(RoundArrays a, GridView g)
     }
     if (lane == 0 && tested) atomicAdd(&st->stat_rtested, (unsigned long long)tested);
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&st->stat_research, nr);
+}
+
+__global__ void __launch_bounds__(1024) rb_coarse(RoundArrays a, GridView g, int what) {
+    const RoundDev* st = a.st;
+    if (st->done || st->err) return;
+    for (int L = a.lc; L < g.nlev; L++) {
+        const LevelView& lv = g.lv[L];
+        const uint32_t b = lv.base, bc = g.lv[L - 1].base, nc = lv.ncells, ncc = g.lv[L - 1].ncells;
+        for (uint32_t c = threadIdx.x; c < nc; c += blockDim.x) {
+            const uint32_t c0 = a.clo[b + c], c1 = c + 1 < nc ? a.clo[b + c + 1] : ncc;
+            if (what == 0) {
+                uint32_t s[kLev] = {};
+                for (uint32_t u = c0; u < c1; u++)
+#pragma unroll
+                    for (int j = 0; j < kLev; j++) s[j] += a.cellAlev[(size_t)(bc + u) * kLev + j];
+#pragma unroll
+                for (int j = 0; j < kLev; j++) a.cellAlev[(size_t)(b + c) * kLev + j] = s[j];
+            } else {
+                uint32_t s = 0;
+                for (uint32_t u = c0; u < c1; u++) s += a.cell_alive[bc + u];
+                a.cell_alive[b + c] = s;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// First child (index at the level below) of every cell of the levels >= lc.
+__global__ void __launch_bounds__(kBlock) coarse_clo_k(const uint32_t* __restrict__ parent, uint32_t nchild,
+                                                      uint32_t* __restrict__ clo) {
+    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < nchild; u += gridDim.x * blockDim.x)
+        if (u == 0 || parent[u] != parent[u - 1]) clo[parent[u]] = u;
 }
 
 // Advances the reverse-list pool past the re-searches' nodes.
@@ -985,8 +1017,10 @@ enum {
     kSCellAlive = 60, kSCellA, kSDgC, kSDgO, kSDgD, kSSurvOff, kSSurvList, kSSurvBucket, kSCS, kSGrpLo, kSGrpHi,
     kSGSafe, kSAPts, kSAStart, kSAFlag, kSAPos,
     kSOvfK0 = 89, kSOvfV0, kSOvfK1, kSOvfV1, kSSegFirst, kSSeg, kSOff, kSSegCnt, kSSegGlob, kSSegTopC, kSSegTopO,
-    kSPool0 = 101, kSPool1
+    kSPool0 = 101, kSPool1, kSClo
 };
+// levels with at most this many cells are counted by rb_coarse
+constexpr uint32_t kCoarseCells = 4096;
 static_assert(kSSurv < 40, "scratch slots overlap the scan's");
 static_assert(kSAPos < 76 && kSSegTopO < kScratchSlots, "scratch slots beyond the context's table");
 
@@ -1094,6 +1128,7 @@ int launch_round(Ctx* c, RoundArrays& a, const GridView& g, const GridView& gs) 
     if (rc) return rc;
     hipLaunchKernelGGL(rb_remove, dim3(G), dim3(kBlock), 0, c->stream, a, g);
     hipLaunchKernelGGL(rb_remove_end, dim3(1), dim3(1), 0, c->stream, a);
+    launch_coarse(c, a, g, 1);
     hipLaunchKernelGGL(rb_touch_recost, dim3(G), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_research<K>, dim3(G), dim3(kBlock), 0, c->stream, a, gs);
     hipLaunchKernelGGL(rb_pool_end, dim3(1), dim3(1), 0, c->stream, a);
@@ -1153,6 +1188,10 @@ int run_rounds(Ctx* c, RoundArrays& a, const GridView& g, uint32_t n) {
 
 }  // namespace
 
+void launch_coarse(Ctx* c, const RoundArrays& a, const GridView& g, int what) {
+    if (a.lc < g.nlev) hipLaunchKernelGGL(rb_coarse, dim3(1), dim3(1024), 0, c->stream, a, g, what);
+}
+
 int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, const int64_t* h_off,
              const int64_t* h_keep, int nseg, int32_t* kept, int32_t* order, uint64_t* order_cost) {
     const GridView& g = grid.v;
@@ -1210,6 +1249,13 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, cons
     ALLOC(pool_next, kSPoolN, pool_cap * 4);
     ALLOC(cell_alive, kSCellAlive, (size_t)tcells * 4);
     ALLOC(cellAlev, kSCellA, (size_t)tcells * kLev * 4);
+    ALLOC(clo, kSClo, (size_t)tcells * 4);
+    a.lc = g.nlev;
+    for (int L = 1; L < g.nlev; L++)
+        if (g.lv[L].ncells <= kCoarseCells) {
+            a.lc = L;
+            break;
+        }
     ALLOC(surv_off, kSSurvOff, (size_t)(ncells0 + 1) * 4);
     ALLOC(surv_list, kSSurvList, (size_t)n * 4);
     ALLOC(surv_bucket, kSSurvBucket, (size_t)n * 4);
@@ -1249,6 +1295,9 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, cons
     for (int L = 0; L < g.nlev; L++)
         hipLaunchKernelGGL(cell_count_k, dim3(gfor(g.lv[L].ncells)), dim3(kBlock), 0, c->stream, g.lv[L].start,
                            g.lv[L].ncells, a.cell_alive + g.lv[L].base);
+    for (int L = a.lc; L < g.nlev; L++)
+        hipLaunchKernelGGL(coarse_clo_k, dim3(gfor(g.lv[L - 1].ncells)), dim3(kBlock), 0, c->stream, g.lv[L - 1].parent,
+                           g.lv[L - 1].ncells, a.clo + g.lv[L].base);
     hipLaunchKernelGGL(rd_init, dim3(1), dim3(1), 0, c->stream, a.st, n, target, (uint32_t)pool_cap, frac);
     PDD_HIP(c, hipGetLastError());
 
