@@ -50,6 +50,8 @@ struct RoundArrays {
     uint32_t* touched;
     uint32_t* surv;
     uint32_t* alive_list[2];
+    int4* apts;              // alive search view (.w = -1 once removed)
+    const uint32_t* vpos;    // [n] view position of each point alive when it was built
     uint32_t* pool_list[2];  // candidate pool (see RoundDev)
     uint32_t* A;
     uint32_t* cand[2];

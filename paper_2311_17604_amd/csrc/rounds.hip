@@ -595,6 +595,7 @@ __global__ void __launch_bounds__(kBlock) rb_remove(RoundArrays a, GridView g) {
             a.ev_cost[st->removed + p] = a.cost[x];
             a.ev_orig[st->removed + p] = a.pts[x].w;
             a.alive[x] = 0;
+            a.apts[a.vpos[x]].w = -1;  // dead in the search view
             const uint32_t sx = seg_of_pt(a, x);
             if (run_cnt && sx != run_seg) {
                 atomicSub(&a.seg_left[run_seg], run_cnt);
@@ -826,22 +827,22 @@ __global__ void rb_pool_end(RoundArrays a) {
 // reverse lists
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(kBlock) rev_count_k(RoundArrays a, uint32_t n, uint32_t* deg) {
-    for (uint32_t z = blockIdx.x * blockDim.x + threadIdx.x; z < n; z += gridDim.x * blockDim.x) {
-        if (!a.alive[z]) continue;
-        const int c = a.cnt[z];
-        for (int j = 0; j < c; j++) atomicAdd(&deg[a.nbr[(size_t)z * a.K + j]], 1u);
-    }
-}
-
-__global__ void __launch_bounds__(kBlock) rev_fill_k(RoundArrays a, uint32_t n, uint32_t* cursor) {
-    for (uint32_t z = blockIdx.x * blockDim.x + threadIdx.x; z < n; z += gridDim.x * blockDim.x) {
-        if (!a.alive[z]) continue;
-        const int c = a.cnt[z];
-        for (int j = 0; j < c; j++) {
-            const uint32_t slot = atomicAdd(&cursor[a.nbr[(size_t)z * a.K + j]], 1u);
-            a.rev_src[slot] = (int32_t)z;
-        }
+// Reverse lists of the alive points' list entries that are alive (a removed
+// entry is never removed again, so nothing needs to find it): one thread per
+// (point of the list L, entry).  fill = 0 counts, fill = 1 places.
+__global__ void __launch_bounds__(kBlock) rev_k(RoundArrays a, const uint32_t* __restrict__ L, uint32_t m,
+                                                uint32_t* cursor, int fill) {
+    const int K = a.K;
+    const uint64_t total = (uint64_t)m * (uint64_t)K;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t z = L[t / (uint32_t)K];
+        const int j = (int)(t % (uint32_t)K);
+        if (!a.alive[z] || j >= a.cnt[z]) continue;
+        const uint32_t y = (uint32_t)a.nbr[(size_t)z * K + j];
+        if (!a.alive[y]) continue;
+        if (fill) a.rev_src[atomicAdd(&cursor[y], 1u)] = (int32_t)z;
+        else atomicAdd(&cursor[y], 1u);
     }
 }
 
@@ -1024,16 +1025,18 @@ constexpr uint32_t kCoarseCells = 4096;
 static_assert(kSSurv < 40, "scratch slots overlap the scan's");
 static_assert(kSAPos < 76 && kSSegTopO < kScratchSlots, "scratch slots beyond the context's table");
 
-int build_reverse(Ctx* c, RoundArrays& a, uint32_t n) {
+// L, m: a list holding every alive point (dead entries are skipped)
+int build_reverse(Ctx* c, RoundArrays& a, uint32_t n, const uint32_t* L, uint32_t m) {
     uint32_t* deg = (uint32_t*)scratch(c, kSTmp, (size_t)(n + 1) * 4);
     if (!deg) return PDD_ENOMEM;
     int rc;
     if ((rc = fill_u32(c, deg, 0, n + 1))) return rc;
-    hipLaunchKernelGGL(rev_count_k, dim3(gfor(n)), dim3(kBlock), 0, c->stream, a, n, deg);
+    const unsigned gr = (unsigned)std::min<uint64_t>(((uint64_t)m * a.K + kBlock - 1) / kBlock, 16384u);
+    hipLaunchKernelGGL(rev_k, dim3(std::max(gr, 1u)), dim3(kBlock), 0, c->stream, a, L, m, deg, 0);
     PDD_HIP(c, hipGetLastError());
     if ((rc = exclusive_scan_u32(c, deg, a.rev_off, n + 1, nullptr))) return rc;
     PDD_HIP(c, hipMemcpyAsync(deg, a.rev_off, (size_t)(n + 1) * 4, hipMemcpyDeviceToDevice, c->stream));
-    hipLaunchKernelGGL(rev_fill_k, dim3(gfor(n)), dim3(kBlock), 0, c->stream, a, n, deg);
+    hipLaunchKernelGGL(rev_k, dim3(std::max(gr, 1u)), dim3(kBlock), 0, c->stream, a, L, m, deg, 1);
     PDD_HIP(c, hipGetLastError());
     if ((rc = fill_u32(c, (uint32_t*)a.head, 0xFFFFFFFFu, n))) return rc;
     hipLaunchKernelGGL(rev_reset_k, dim3(1), dim3(1), 0, c->stream, a);
@@ -1042,7 +1045,7 @@ int build_reverse(Ctx* c, RoundArrays& a, uint32_t n) {
 }
 
 // (Re)builds the alive search view gs of grid g.
-int build_alive_view(Ctx* c, const RoundArrays& a, const GridView& g, GridView* gs) {
+int build_alive_view(Ctx* c, RoundArrays& a, const GridView& g, GridView* gs) {
     const uint32_t n = g.n;
     int4* apts = (int4*)scratch(c, kSAPts, (size_t)n * sizeof(int4));
     uint32_t* astart = (uint32_t*)scratch(c, kSAStart, ((size_t)g.total_cells + g.nlev) * 4);
@@ -1054,6 +1057,8 @@ int build_alive_view(Ctx* c, const RoundArrays& a, const GridView& g, GridView* 
     int rc = exclusive_scan_u32(c, flag, pos, n, pos + n);
     if (rc) return rc;
     hipLaunchKernelGGL(av_pack_k, dim3(gfor(n)), dim3(kBlock), 0, c->stream, g.pts, a.alive, pos, n, apts);
+    a.apts = apts;
+    a.vpos = pos;
     *gs = g;
     gs->pts = apts;
     size_t off = 0;
@@ -1171,7 +1176,7 @@ int run_rounds(Ctx* c, RoundArrays& a, const GridView& g, uint32_t n) {
         // rebuild the reverse lists when the appended chains overflowed or
         // grew longer than six nodes per alive point on average
         if (hst->overflow || hst->pool_count > 6 * hst->n_alive_new) {
-            if ((rc = build_reverse(c, a, n))) return rc;
+            if ((rc = build_reverse(c, a, n, a.alive_list[hst->apar], hst->n_list))) return rc;
             c->stats[3]++;
         }
         // re-pack the alive search view once a third of its points are gone
@@ -1305,7 +1310,7 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, cons
     mark(c, kPhGrid);
     if ((rc = knn_all(c, g, k, K, ko, &c->stats[4]))) return rc;
     mark(c, kPhKnn);
-    if ((rc = build_reverse(c, a, n))) return rc;
+    if ((rc = build_reverse(c, a, n, a.alive_list[0], n))) return rc;
     mark(c, kPhReverse);
     c->stats[3] = 0;
 

@@ -16,7 +16,8 @@ namespace pdd {
 //           point's id is its position
 //   kAlive  alive points; the grid view holds a compacted copy of the points
 //           that were alive when it was built (same cells, same Morton
-//           order), each with its sorted position in .w
+//           order), each with its sorted position in .w, set to -1 when the
+//           point is removed
 enum SearchMode { kAll = 0, kAlive = 1 };
 
 struct SearchCtx {
@@ -138,7 +139,7 @@ __device__ inline uint32_t wave_scan(const GridView& g, uint32_t q, int4 qp, con
             const int4 p = g.pts[pos];
             j = MODE == kAll ? pos : (uint32_t)p.w;
             bool ok = j != q;
-            if (MODE != kAll && ok) ok = sc.alive[j] != 0;
+            if (MODE != kAll && ok) ok = p.w >= 0;
             if (ok && skip && abs(((p.x - g.minx) >> ps) - px) <= 1 && abs(((p.y - g.miny) >> ps) - py) <= 1 &&
                 abs(((p.z - g.minz) >> ps) - pz) <= 1)
                 ok = false;
