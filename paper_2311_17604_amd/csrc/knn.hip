@@ -9,7 +9,7 @@ namespace {
 
 constexpr int kSlotKnnStat = 88;
 constexpr int kSlotTileAnc = 124, kSlotTileFlag = 125, kSlotTilePos = 126, kSlotTileList = 127,
-              kSlotTileFB = 100;
+              kSlotTileFB = 100, kSlotTileSorted = 104;
 constexpr int kTileCap = 2048;  // candidates of one tile held in LDS (11-bit index)
 constexpr int kTileCells = kBlock; // cells of one tile's region, at most
 
@@ -69,102 +69,179 @@ __device__ inline uint64_t region_gap2(int u, int r0, int w, int s, int cmax) {
     return g;
 }
 
+// The region searched for the points anchored in one cell (global cell id
+// gid): cells of level rl, per axis from r0 over w cells.  By default the
+// cells of level L-1 from half an edge below the anchor cell to half an edge
+// above it (level 0: the 3x3x3 block); with a predicted radius r, the cells
+// of the finest level at which the anchor cell grown by r spans at most 6
+// cells per axis, when they cover less than the default region.
+struct TileRegion {
+    int L;           // anchor level
+    uint32_t c;      // anchor cell at level L
+    uint32_t sg;     // segment of the anchor cell
+    int ac[3];       // anchor cell coordinates at level L
+    int rl;          // level of the region's cells
+    int r0[3], w[3];
+    bool pred;       // a predicted radius was given for this anchor
+};
+
+__device__ inline TileRegion tile_region(const GridView& g, uint32_t gid, const uint64_t* __restrict__ rhat2) {
+    TileRegion R;
+    int L = 0;
+    while (L + 1 < g.nlev && gid >= g.lv[L + 1].base) L++;
+    const LevelView& lv = g.lv[L];
+    R.L = L;
+    R.c = gid - lv.base;
+    const uint64_t code = lv.key[R.c];
+    R.sg = (uint32_t)(code >> lv.segshift);
+    const uint64_t mc = code & ((1ull << lv.segshift) - 1ull);
+    R.ac[0] = (int)compact21(mc);
+    R.ac[1] = (int)compact21(mc >> 1);
+    R.ac[2] = (int)compact21(mc >> 2);
+    R.rl = L >= 1 ? L - 1 : 0;
+    for (int a = 0; a < 3; a++) {
+        R.r0[a] = L >= 1 ? 2 * R.ac[a] - 1 : R.ac[a] - 1;
+        R.w[a] = L >= 1 ? 4 : 3;
+    }
+    const uint64_t rp2 = (rhat2 && L >= 1) ? rhat2[gid] : 0ull;
+    R.pred = rp2 != 0;
+    if (rp2) {
+        const int r = (int)sqrt((double)rp2) + 1;
+        for (int l = 0; l <= L; l++) {
+            const int sl = g.lv[l].s;
+            bool ok = true;
+            int q0[3], qw[3];
+            for (int a = 0; a < 3; a++) {
+                const int lo = max((R.ac[a] << lv.s) - r, 0), hi = (((R.ac[a] + 1) << lv.s) - 1) + r;
+                q0[a] = lo >> sl;
+                qw[a] = min(hi >> sl, g.lv[l].cmax[a]) - q0[a] + 1;
+                if (qw[a] > 6) ok = false;
+            }
+            if (ok) {
+                // taken only when smaller than the default region
+                const int64_t vol = (int64_t)qw[0] * qw[1] * qw[2] << (3 * sl);
+                const int64_t vdef = (int64_t)R.w[0] * R.w[1] * R.w[2] << (3 * g.lv[R.rl].s);
+                if (vol < vdef) {
+                    R.rl = l;
+                    for (int a = 0; a < 3; a++) {
+                        R.r0[a] = q0[a];
+                        R.w[a] = qw[a];
+                    }
+                }
+                break;
+            }
+        }
+    }
+    return R;
+}
+
+// Largest region edge (mm) for which every squared distance between two of
+// its points is below 2^21 (3 * 835^2 < 2^21), so that a candidate key
+// (d2 << 11 | slot) fits 32 bits.
+constexpr int kKey32Edge = 836;
+
+// Splits the tiles by key width: regions within kKey32Edge per axis go to
+// the front of `sorted` (count cnt[0]), the others to the back (cnt[1]).
+__global__ void __launch_bounds__(kBlock) tile_class_k(GridView g, const uint32_t* __restrict__ tiles, uint32_t ntiles,
+                                                       const uint64_t* __restrict__ rhat2,
+                                                       uint32_t* __restrict__ sorted, uint32_t* __restrict__ cnt) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x) {
+        const uint32_t gid = tiles[t];
+        const TileRegion R = tile_region(g, gid, rhat2);
+        const int s = g.lv[R.rl].s;
+        bool small = true;
+        for (int a = 0; a < 3; a++)
+            if (((int64_t)R.w[a] << s) > kKey32Edge) small = false;
+        if (small) sorted[atomicAdd(&cnt[0], 1u)] = gid;
+        else sorted[ntiles - 1u - atomicAdd(&cnt[1], 1u)] = gid;
+    }
+}
+
+template <typename KT>
+__device__ inline KT tile_d2(int ax, int ay, int az, int bx, int by, int bz);
+template <>
+__device__ inline uint32_t tile_d2<uint32_t>(int ax, int ay, int az, int bx, int by, int bz) {
+    const uint32_t dx = (uint32_t)abs(ax - bx), dy = (uint32_t)abs(ay - by), dz = (uint32_t)abs(az - bz);
+    return __umul24(dx, dx) + __umul24(dy, dy) + __umul24(dz, dz);
+}
+template <>
+__device__ inline uint64_t tile_d2<uint64_t>(int ax, int ay, int az, int bx, int by, int bz) {
+    return dist2(ax, ay, az, bx, by, bz);
+}
+
+// squared distance from a point at offset u (relative to the region's
+// corner) to the cell at offset o (cells of edge 2^s) along one axis
+template <typename KT>
+__device__ inline KT box_gap2(int u, int o, int s) {
+    const int lo = o << s, hi = lo + (1 << s) - 1;
+    const int d = max(max(lo - u, u - hi), 0);
+    return (KT)d * (KT)d;
+}
+
 // LDS-tiled k-NN: one block per anchor cell (the finest cell holding K + 1
-// points).  The block loads the points of the region around the cell into
-// LDS once: at level L >= 1 the 4x4x4 cells of level L-1 centred on it (the
-// cell and half its edge around it), at level 0 its 3x3x3 block.  Each
-// thread then takes one point anchored there and scans the whole region
-// from LDS, keeping its K smallest (d2, slot) keys in registers.  The list
-// is exact when its K-th distance is within the region's distance to the
-// nearest cell outside it; other points (and tiles whose region holds more
-// than kTileCap points) go to the fallback list for the wave search.
-template <int K>
+// points).  The block loads the points of the cell's region (tile_region)
+// into LDS once, ordered by cell: cells that overlap the anchor cell first,
+// then cells beside it across a face, an edge, a corner.  Each thread takes
+// one point anchored there and walks the cells, keeping its K smallest
+// (d2, slot) keys in registers; a wave passes over a cell when no lane's
+// K-th distance reaches beyond the cell's distance from that lane's point.
+// KT is the key type: 32 bits for tiles whose region fits kKey32Edge, else
+// 64.  The list is exact when its K-th distance is within the region's
+// distance to the nearest cell outside it; other points (and tiles whose
+// region holds more than kTileCap points) go to the fallback list for the
+// wave search.  part 0 takes tiles[0, tcnt[0]), part 1 tiles[ntiles -
+// tcnt[1], ntiles).
+template <int K, typename KT>
 __global__ void __launch_bounds__(kBlock) knn_tile_k(GridView g, int k, const uint32_t* __restrict__ tiles,
-                                                     uint32_t ntiles, const uint32_t* __restrict__ anc_of,
+                                                     const uint32_t* __restrict__ tcnt, uint32_t ntiles, int part,
+                                                     const uint32_t* __restrict__ anc_of,
                                                      const uint64_t* __restrict__ rhat2, int32_t* __restrict__ nbr,
                                                      uint8_t* __restrict__ cnt, uint64_t* __restrict__ cost,
                                                      int64_t* __restrict__ r2k, uint32_t* __restrict__ fb,
                                                      unsigned long long* __restrict__ stat) {
+    constexpr KT kEmpty = (KT)~(KT)0;
     __shared__ int4 cand[kTileCap];
-    __shared__ uint32_t cst[kTileCells], cex[kTileCells + 1];
-    __shared__ uint32_t s_q[kBlock], s_pack[kBlock / kWave + 1], s_npack, s_nin;
+    __shared__ uint32_t cst[kTileCells], cex[kTileCells + 1], coff[kTileCells];
+    __shared__ uint32_t s_q[kBlock], s_pack[kBlock / kWave + 1], s_npack;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const uint32_t tb = part == 0 ? 0u : ntiles - tcnt[1];
+    const uint32_t te = part == 0 ? tcnt[0] : ntiles;
     uint32_t tested = 0, hits = 0, misses = 0;
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    for (uint32_t t = tb + blockIdx.x; t < te; t += gridDim.x) {
         const uint32_t gid = tiles[t];
-        int L = 0;
-        while (L + 1 < g.nlev && gid >= g.lv[L + 1].base) L++;
-        const LevelView& lv = g.lv[L];
-        const uint32_t c = gid - lv.base;
-        const uint64_t code = lv.key[c];
-        const uint32_t sg = (uint32_t)(code >> lv.segshift);
-        const uint64_t mc = code & ((1ull << lv.segshift) - 1ull);
-        const int ac[3] = {(int)compact21(mc), (int)compact21(mc >> 1), (int)compact21(mc >> 2)};
-        // the region: by default the cells of level L-1 from half an edge
-        // below the anchor cell to half an edge above it (level 0: the
-        // 3x3x3 block); with a predicted radius r, the cells of the finest
-        // level at which the anchor cell grown by r spans at most 6 cells per
-        // axis, when they cover less than the default region
-        int rl = L >= 1 ? L - 1 : 0;
-        int r0[3], w[3];
-        for (int a = 0; a < 3; a++) {
-            r0[a] = L >= 1 ? 2 * ac[a] - 1 : ac[a] - 1;
-            w[a] = L >= 1 ? 4 : 3;
-        }
-        const uint64_t rp2 = (rhat2 && L >= 1) ? rhat2[gid] : 0ull;
-        if (rp2) {
-            const int r = (int)sqrt((double)rp2) + 1;
-            for (int l = 0; l <= L; l++) {
-                const int sl = g.lv[l].s;
-                bool ok = true;
-                int q0[3], qw[3];
-                for (int a = 0; a < 3; a++) {
-                    const int lo = max((ac[a] << lv.s) - r, 0), hi = (((ac[a] + 1) << lv.s) - 1) + r;
-                    q0[a] = lo >> sl;
-                    qw[a] = min(hi >> sl, g.lv[l].cmax[a]) - q0[a] + 1;
-                    if (qw[a] > 6) ok = false;
-                }
-                if (ok) {
-                    // taken only when smaller than the default region
-                    const int64_t vol = (int64_t)qw[0] * qw[1] * qw[2] << (3 * sl);
-                    const int64_t vdef = (int64_t)w[0] * w[1] * w[2] << (3 * g.lv[rl].s);
-                    if (vol < vdef) {
-                        rl = l;
-                        for (int a = 0; a < 3; a++) {
-                            r0[a] = q0[a];
-                            w[a] = qw[a];
-                        }
-                    }
-                    break;
-                }
-            }
-        }
-        const LevelView& rv = g.lv[rl];
-        const int ncell = w[0] * w[1] * w[2];
-        // look the cells up (one per thread) and order them: cells that
-        // overlap the anchor cell first, so the lists fill with near points
-        // early and later candidates rarely enter
-        uint32_t st = 0, n = 0;
-        bool inner = false;
+        const TileRegion R = tile_region(g, gid, rhat2);
+        const LevelView& lv = g.lv[R.L];
+        const LevelView& rv = g.lv[R.rl];
+        const int s = rv.s;
+        const int ncell = R.w[0] * R.w[1] * R.w[2];
+        // look the cells up (one per thread); rank = axes along which the
+        // cell lies outside the anchor cell
+        uint32_t st = 0, n = 0, off = 0;
+        int rank = 4;
         if (tid < ncell) {
-            const int ix = tid % w[0], iy = (tid / w[0]) % w[1], iz = tid / (w[0] * w[1]);
-            const int x = r0[0] + ix, y = r0[1] + iy, z = r0[2] + iz;
+            const int ix = tid % R.w[0], iy = (tid / R.w[0]) % R.w[1], iz = tid / (R.w[0] * R.w[1]);
+            const int x = R.r0[0] + ix, y = R.r0[1] + iy, z = R.r0[2] + iz;
             const int sh = lv.s - rv.s;
-            inner = (x >> sh) == ac[0] && (y >> sh) == ac[1] && (z >> sh) == ac[2];
+            rank = ((x >> sh) != R.ac[0]) + ((y >> sh) != R.ac[1]) + ((z >> sh) != R.ac[2]);
+            off = (uint32_t)ix | ((uint32_t)iy << 8) | ((uint32_t)iz << 16);
             if (x >= 0 && y >= 0 && z >= 0 && x <= rv.cmax[0] && y <= rv.cmax[1] && z <= rv.cmax[2]) {
-                const uint32_t cc = hash_find(rv.hkeys, rv.hvals, rv.hmask, cell_code(rv, sg, x, y, z));
+                const uint32_t cc = hash_find(rv.hkeys, rv.hvals, rv.hmask, cell_code(rv, R.sg, x, y, z));
                 if (cc != kNone) {
                     st = rv.start[cc];
                     n = rv.start[cc + 1] - st;
                 }
             }
         }
-        const uint32_t si = block_pack(tid < ncell && inner, s_pack, &s_nin);
-        const uint32_t so = block_pack(tid < ncell && !inner, s_pack, &s_npack);
+        uint32_t slot = 0, acc = 0;
+        for (int r = 0; r < 4; r++) {
+            const uint32_t sr = block_pack(rank == r, s_pack, &s_npack);
+            if (rank == r) slot = acc + sr;
+            acc += s_npack;
+        }
         if (tid < ncell) {
-            const uint32_t slot = inner ? si : s_nin + so;
             cst[slot] = st;
             cex[slot] = n;
+            coff[slot] = off;
         }
         __syncthreads();
         // exclusive scan of the ordered counts (up to kTileCells = kBlock)
@@ -180,12 +257,11 @@ __global__ void __launch_bounds__(kBlock) knn_tile_k(GridView g, int k, const ui
             __syncthreads();
             uint32_t base = 0;
             for (int i = 0; i < wv; i++) base += s_pack[i];
-            cex[tid] = tid < ncell ? base + incl - v : 0xFFFFFFFFu;
-            if (tid == kBlock - 1) {
-                uint32_t tot = 0;
-                for (int i = 0; i < kBlock / kWave; i++) tot += s_pack[i];
-                cex[kTileCells] = tot;
-            }
+            uint32_t tot = 0;
+            for (int i = 0; i < kBlock / kWave; i++) tot += s_pack[i];
+            // cex[l] = first slot of cell l; cex[l] = total past the last cell
+            cex[tid] = tid < ncell ? base + incl - v : tot;
+            if (tid == kBlock - 1) cex[kTileCells] = tot;
         }
         __syncthreads();
         const uint32_t total = cex[kTileCells];
@@ -203,12 +279,12 @@ __global__ void __launch_bounds__(kBlock) knn_tile_k(GridView g, int k, const ui
         __syncthreads();
         // the points anchored here, packed onto the first threads (waves
         // past the last query skip the scan)
-        const uint32_t q0 = lv.start[c], q1 = lv.start[c + 1];
+        const uint32_t q0 = lv.start[R.c], q1 = lv.start[R.c + 1];
         for (uint32_t qb = q0; qb < q1; qb += blockDim.x) {
             const uint32_t qq = qb + tid;
             const bool anch = qq < q1 && anc_of[qq] == gid;
-            const uint32_t slot = block_pack(anch, s_pack, &s_npack);
-            if (anch) s_q[slot] = qq;
+            const uint32_t qslot = block_pack(anch, s_pack, &s_npack);
+            if (anch) s_q[qslot] = qq;
             __syncthreads();
             const uint32_t nq = s_npack;
             const bool mine = (uint32_t)tid < nq;
@@ -216,21 +292,24 @@ __global__ void __launch_bounds__(kBlock) knn_tile_k(GridView g, int k, const ui
             __syncthreads();
             if (!fits) {
                 if (mine) fb[atomicAdd(&stat[3], 1ull)] = q;
-                if (mine && rp2) misses++;
+                if (mine && R.pred) misses++;
                 continue;
             }
             if ((uint32_t)(tid & ~(kWave - 1)) >= nq) continue;  // whole wave without a query
             int4 qp = make_int4(0, 0, 0, 0);
             if (mine) qp = g.pts[q];
-            uint64_t top[K];
+            // the point relative to the region's corner
+            const int ux = qp.x - g.minx - R.r0[0] * (1 << s), uy = qp.y - g.miny - R.r0[1] * (1 << s),
+                      uz = qp.z - g.minz - R.r0[2] * (1 << s);
+            KT top[K];
 #pragma unroll
-            for (int e = 0; e < K; e++) top[e] = ~0ull;
+            for (int e = 0; e < K; e++) top[e] = kEmpty;
             // candidates below the lane's K-th key wait in a 4-entry buffer;
             // the (wave-wide) sorted insertion runs when some lane's buffer
             // is full, and at the end
-            uint64_t b0 = ~0ull, b1 = ~0ull, b2 = ~0ull, b3 = ~0ull;
+            KT b0 = kEmpty, b1 = kEmpty, b2 = kEmpty, b3 = kEmpty;
             int nb = 0;
-            auto insert = [&](uint64_t key) {
+            auto insert = [&](KT key) {
                 if (key < top[K - 1]) {
 #pragma unroll
                     for (int e = K - 1; e > 0; e--) {
@@ -247,32 +326,42 @@ __global__ void __launch_bounds__(kBlock) knn_tile_k(GridView g, int k, const ui
                 if (nb > 3) insert(b3);
                 nb = 0;
             };
-            for (uint32_t u = 0; u < total; u++) {
-                const int4 p = cand[u];
-                const uint64_t key = (dist2(qp.x, qp.y, qp.z, p.x, p.y, p.z) << 11) | u;
-                if (mine && (uint32_t)p.w != q && key < top[K - 1]) {
-                    b3 = nb == 3 ? key : b3;
-                    b2 = nb == 2 ? key : b2;
-                    b1 = nb == 1 ? key : b1;
-                    b0 = nb == 0 ? key : b0;
-                    nb++;
+            for (int l = 0; l < ncell; l++) {
+                const uint32_t u0 = cex[l], u1 = cex[l + 1];
+                if (u0 == u1) continue;
+                // no candidate of a cell at box distance >= the lane's K-th
+                // distance can change the lane's distances (a tie at the
+                // K-th distance leaves their multiset as it is)
+                const uint32_t o = coff[l];
+                const KT bd = box_gap2<KT>(ux, (int)(o & 255u), s) + box_gap2<KT>(uy, (int)((o >> 8) & 255u), s) +
+                              box_gap2<KT>(uz, (int)(o >> 16), s);
+                if (!__any(mine && bd < (KT)(top[K - 1] >> 11))) continue;
+                if (mine) tested += u1 - u0;
+                for (uint32_t u = u0; u < u1; u++) {
+                    const int4 p = cand[u];
+                    const KT key = (tile_d2<KT>(qp.x, qp.y, qp.z, p.x, p.y, p.z) << 11) | (KT)u;
+                    if (mine && (uint32_t)p.w != q && key < top[K - 1]) {
+                        b3 = nb == 3 ? key : b3;
+                        b2 = nb == 2 ? key : b2;
+                        b1 = nb == 1 ? key : b1;
+                        b0 = nb == 0 ? key : b0;
+                        nb++;
+                    }
+                    if (__any(nb == 4)) flush();
                 }
-                if (__any(nb == 4)) flush();
             }
             flush();
             if (!mine) continue;
-            tested += total;
             int filled = 0;
 #pragma unroll
-            for (int e = 0; e < K; e++) filled += top[e] != ~0ull;
-            const int s = rv.s;
-            uint64_t gap = region_gap2(qp.x - g.minx, r0[0], w[0], s, rv.cmax[0]);
-            const uint64_t gy = region_gap2(qp.y - g.miny, r0[1], w[1], s, rv.cmax[1]);
-            const uint64_t gz = region_gap2(qp.z - g.minz, r0[2], w[2], s, rv.cmax[2]);
+            for (int e = 0; e < K; e++) filled += top[e] != kEmpty;
+            uint64_t gap = region_gap2(qp.x - g.minx, R.r0[0], R.w[0], s, rv.cmax[0]);
+            const uint64_t gy = region_gap2(qp.y - g.miny, R.r0[1], R.w[1], s, rv.cmax[1]);
+            const uint64_t gz = region_gap2(qp.z - g.minz, R.r0[2], R.w[2], s, rv.cmax[2]);
             if (gy < gap) gap = gy;
             if (gz < gap) gap = gz;
-            const bool ok = gap == ~0ull || (filled == K && (top[K - 1] >> 11) <= gap);
-            if (rp2) {
+            const bool ok = gap == ~0ull || (filled == K && (uint64_t)(top[K - 1] >> 11) <= gap);
+            if (R.pred) {
                 if (ok) hits++;
                 else misses++;
             }
@@ -284,10 +373,10 @@ __global__ void __launch_bounds__(kBlock) knn_tile_k(GridView g, int k, const ui
             uint64_t wsum = 0, dk = 0;
 #pragma unroll
             for (int e = 0; e < K; e++) {
-                const uint64_t d = top[e] >> 11;
+                const uint64_t d = (uint64_t)(top[e] >> 11);
                 if (e < use) wsum += cost_term(d);
                 if (e == use - 1) dk = d;
-                nbr[(size_t)q * K + e] = e < filled ? cand[top[e] & 2047u].w : -1;
+                nbr[(size_t)q * K + e] = e < filled ? cand[(uint32_t)(top[e] & (KT)2047)].w : -1;
             }
             cnt[q] = (uint8_t)filled;
             cost[q] = wsum;
@@ -429,8 +518,18 @@ int knn_tiled(Ctx* c, const GridView& g, int k, KnnOut out, const uint64_t* rhat
     const uint32_t ntiles = h[0];
     uint32_t* fb = (uint32_t*)scratch(c, kSlotTileFB, (size_t)g.n * 4);
     if (!fb) return PDD_ENOMEM;
-    hipLaunchKernelGGL(knn_tile_k<K>, dim3(std::min<uint32_t>(std::max<uint32_t>(ntiles, 1u), 65535u)), block, 0,
-                       c->stream, g, k, tiles, ntiles, anc_of, rhat2, out.nbr, out.cnt, out.cost, out.r2k, fb, stat);
+    uint32_t* sorted = (uint32_t*)scratch(c, kSlotTileSorted, (size_t)std::max<uint32_t>(ntiles, 1u) * 4);
+    if (!sorted) return PDD_ENOMEM;
+    uint32_t* tcnt = (uint32_t*)(stat + 4);
+    hipLaunchKernelGGL(tile_class_k, dim3(std::min<uint32_t>((ntiles + kBlock - 1) / kBlock + 1, 16384u)), block, 0,
+                       c->stream, g, tiles, ntiles, rhat2, sorted, tcnt);
+    PDD_HIP(c, hipGetLastError());
+    const dim3 tgrid(std::min<uint32_t>(std::max<uint32_t>(ntiles, 1u), 65535u));
+    hipLaunchKernelGGL((knn_tile_k<K, uint32_t>), tgrid, block, 0, c->stream, g, k, sorted, tcnt, ntiles, 0, anc_of,
+                       rhat2, out.nbr, out.cnt, out.cost, out.r2k, fb, stat);
+    PDD_HIP(c, hipGetLastError());
+    hipLaunchKernelGGL((knn_tile_k<K, uint64_t>), tgrid, block, 0, c->stream, g, k, sorted, tcnt, ntiles, 1, anc_of,
+                       rhat2, out.nbr, out.cnt, out.cost, out.r2k, fb, stat);
     PDD_HIP(c, hipGetLastError());
     hipLaunchKernelGGL(knn_list_k<K>, dim3(2048), block, 0, c->stream, g, k, fb, stat + 3, out.nbr, out.cnt, out.cost,
                        out.r2k, stat);
@@ -440,9 +539,10 @@ int knn_tiled(Ctx* c, const GridView& g, int k, KnnOut out, const uint64_t* rhat
 
 int knn_all(Ctx* c, const GridView& g, int k, int K, KnnOut out, int64_t* fallbacks) {
     if (fallbacks) *fallbacks = 0;
-    unsigned long long* stat = (unsigned long long*)scratch(c, kSlotKnnStat, 4 * sizeof(unsigned long long));
+    // 4 counters, then the two tile counts of knn_tiled
+    unsigned long long* stat = (unsigned long long*)scratch(c, kSlotKnnStat, 5 * sizeof(unsigned long long));
     if (!stat) return PDD_ENOMEM;
-    int rc = fill_u32(c, (uint32_t*)stat, 0, 8);
+    int rc = fill_u32(c, (uint32_t*)stat, 0, 10);
     if (rc) return rc;
     const uint64_t* r2 = nullptr;
     if (c->pred_on && c->pred_ready && (rc = pred_radii(c, g, K, &r2))) return rc;
