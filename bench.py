@@ -205,7 +205,7 @@ def main():
     knn_ms = ph["knn"]
     achieved = algo / (knn_ms * 1e-3) / 1e9
     workload = w.name if args.scale == 1.0 else "%s@%g" % (w.name, args.scale)
-    kname = "knn_tile_k<%d>+knn_list_k<%d>" % (K, K)
+    kname = "knn_tile_k<%d,u32|u64>+knn_list_k<%d>" % (K, K)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(workload, kname),
             "kernel": kname, "algorithmic_bytes_per_launch": algo,
