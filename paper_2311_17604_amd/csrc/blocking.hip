@@ -412,15 +412,28 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
                 const int ci = s_ycls[w][i];
                 if (ci == 1 || (ci == 2 && key_above(cx, ox, s_yc[w][i], s_yo[w][i]))) q++;
             }
+            // x's entries four at a time (ids, then alive flags, then
+            // points, each batch of gathers in flight together); q only
+            // grows, so finishing a chunk after q reaches k changes nothing
             const int cxn = a.cnt[x];
-            for (int j = 0; j < cxn && q < k; j++) {
-                const uint32_t z = (uint32_t)a.nbr[(size_t)x * Kb + j];
-                if (z == y || !a.alive[z]) continue;
-                const int4 pz = a.pts[z];
-                const uint64_t dyz = dist2(pz.x, pz.y, pz.z, py.x, py.y, py.z);
-                if (dyz <= dlast || dyz > dxy) continue;
-                if (a.inA[z] == round && key_above(a.cost[z], pz.w, cx, ox)) continue;
-                q++;
+            const int32_t* nbx = a.nbr + (size_t)x * Kb;
+            for (int j0 = 0; j0 < cxn && q < k; j0 += 4) {
+                const int4 v = *(const int4*)(nbx + j0);
+                const uint32_t zs[4] = {(uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z, (uint32_t)v.w};
+                bool ok[4];
+#pragma unroll
+                for (int i = 0; i < 4; i++) ok[i] = j0 + i < cxn && zs[i] != y && a.alive[zs[i]];
+                int4 pz[4];
+#pragma unroll
+                for (int i = 0; i < 4; i++) pz[i] = ok[i] ? a.pts[zs[i]] : py;
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    if (!ok[i]) continue;
+                    const uint64_t dyz = dist2(pz[i].x, pz[i].y, pz[i].z, py.x, py.y, py.z);
+                    if (dyz <= dlast || dyz > dxy) continue;
+                    if (a.inA[zs[i]] == round && key_above(a.cost[zs[i]], pz[i].w, cx, ox)) continue;
+                    q++;
+                }
             }
             if (q < k) a.blocked[x] = round;
         };

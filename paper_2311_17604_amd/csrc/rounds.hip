@@ -657,12 +657,25 @@ __global__ void __launch_bounds__(kBlock) rb_touch_recost(RoundArrays a) {
             const int32_t* nb = a.nbr + (size_t)z * K;
             int nvalid = 0;
             uint64_t wsum = 0;
-            for (int j = 0; j < c && nvalid < k; j++) {
-                const uint32_t y = (uint32_t)nb[j];
-                if (!a.alive[y]) continue;
-                const int4 py = a.pts[y];
-                wsum += cost_term(dist2(pz.x, pz.y, pz.z, py.x, py.y, py.z));
-                nvalid++;
+            // eight entries at a time (K is a multiple of 8 and every list
+            // starts 32-byte aligned): their ids in two loads, then all their
+            // alive flags, then the points of the alive ones, so that the
+            // gathers of a chunk are in flight together
+            for (int j0 = 0; j0 < c && nvalid < k; j0 += 8) {
+                const int4 v0 = *(const int4*)(nb + j0), v1 = *(const int4*)(nb + j0 + 4);
+                const int32_t ys[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+                bool al[8];
+#pragma unroll
+                for (int i = 0; i < 8; i++) al[i] = j0 + i < c && a.alive[(uint32_t)ys[i]];
+                int4 py[8];
+#pragma unroll
+                for (int i = 0; i < 8; i++) py[i] = al[i] ? a.pts[(uint32_t)ys[i]] : pz;
+#pragma unroll
+                for (int i = 0; i < 8; i++)
+                    if (al[i] && nvalid < k) {
+                        wsum += cost_term(dist2(pz.x, pz.y, pz.z, py[i].x, py[i].y, py[i].z));
+                        nvalid++;
+                    }
             }
             if (nvalid < k && c == K) {
                 rs = true;

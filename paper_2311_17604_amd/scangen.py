@@ -210,18 +210,104 @@ def place_stations(rng: np.random.Generator, count: int, square_m: float,
     return np.array(st)
 
 
+_M64 = (1 << 64) - 1
+
+
+def _mix64(x: np.ndarray) -> np.ndarray:
+    """splitmix64 output function on uint64 arrays (wrapping arithmetic)."""
+    x = x + np.uint64(0x9E3779B97F4A7C15)
+    x = (x ^ (x >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    x = (x ^ (x >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return x ^ (x >> np.uint64(31))
+
+
+def ray_noise(seed: int, station: int, ray: np.ndarray, sigma_mm: float) -> np.ndarray:
+    """Range noise N(0, sigma) of rays ``ray`` (row * cols + column) of one
+    station of a merged cloud.  Counter-based: two uniforms from the
+    splitmix64 hash of (seed, station, ray), then Box-Muller, so that any
+    subset of a scan's rays gets the values the whole scan has."""
+    key = np.array([(seed * 0x100000001B3 + station * 0x9E3779B1) & _M64], dtype=np.uint64)
+    key = _mix64(key)
+    c = ray.astype(np.uint64) << np.uint64(1)
+    u1 = (_mix64(key ^ c) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    u2 = (_mix64(key ^ (c | np.uint64(1))) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    return sigma_mm * np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * math.pi * u2)
+
+
+def station_rays(rows: int, cols: int, o: np.ndarray, scene: Scene, i0: int, i1: int, jcols: np.ndarray,
+                 seed: int, station: int, sigma_mm: float) -> np.ndarray:
+    """Hit points (int32 [.., 3]) of the rays of rows [i0, i1) x columns
+    ``jcols`` (ascending) of one station of a merged cloud, row-major."""
+    el, az = _ray_dirs(rows, cols)
+    el, az = el[i0:i1], az[jcols]
+    nr, nc = i1 - i0, len(jcols)
+    ce, se = np.cos(el)[:, None], np.sin(el)[:, None]
+    dx, dy, dz = ce * np.cos(az)[None, :], ce * np.sin(az)[None, :], np.broadcast_to(se, (nr, nc))
+    t = _exit(o, scene.close_lo, scene.close_hi, dx, dy, dz)
+    col_pos = np.full(cols, -1, dtype=np.int64)
+    col_pos[jcols] = np.arange(nc)
+    for b in range(scene.box_lo.shape[0]):
+        lo, hi = scene.box_lo[b], scene.box_hi[b]
+        b0, b1, jc = _window(o, lo, hi, rows, cols)
+        r0, r1 = max(b0, i0), min(b1, i1)
+        sel = col_pos[jc]
+        sel = sel[sel >= 0]
+        if r0 >= r1 or len(sel) == 0:
+            continue
+        sub = np.ix_(np.arange(r0 - i0, r1 - i0), sel)
+        t[sub] = np.minimum(t[sub], _slab(o, lo, hi, dx[sub], dy[sub], dz[sub]))
+    ray = np.arange(i0, i1, dtype=np.int64)[:, None] * cols + jcols[None, :].astype(np.int64)
+    t = t + ray_noise(seed, station, ray, sigma_mm)
+    out = np.empty((nr, nc, 3), dtype=np.int32)
+    out[..., 0] = np.rint(o[0] + t * dx)
+    out[..., 1] = np.rint(o[1] + t * dy)
+    out[..., 2] = np.rint(o[2] + t * dz)
+    return out.reshape(-1, 3)
+
+
 def multi_station(stations: int, rows: int, cols: int, nboxes: int, square_m: float,
-                  seed: int, sigma_mm: float = 2.0) -> np.ndarray:
+                  seed: int, sigma_mm: float = 2.0, crop: tuple | None = None) -> np.ndarray:
+    """Scans of ``stations`` stations (placed by place_stations) of one
+    scene, concatenated station by station, each row-major.  With ``crop`` =
+    (lo, hi) (mm, xyz) only the points inside that box, in the same order:
+    each station casts just the rays that can reach the box."""
     rng = np.random.Generator(np.random.PCG64(seed))
     st = place_stations(rng, stations, square_m)
     scene = wall_scene(rng, nboxes, 2.0, 50.0, 60.0, 40.0, centres_xy_mm=st)
-    parts = [scan_station(rows, cols, (s[0], s[1]), scene, rng, sigma_mm) for s in st]
+    parts = []
+    for s, c in enumerate(st):
+        o = np.array([c[0], c[1], 1500.0])
+        i0, i1, jcols = 0, rows, np.arange(cols)
+        if crop is not None:
+            lo, hi = np.asarray(crop[0], dtype=np.float64), np.asarray(crop[1], dtype=np.float64)
+            if not (lo[0] <= o[0] <= hi[0] and lo[1] <= o[1] <= hi[1]):
+                i0, i1, jcols = _window(o, lo, hi, rows, cols)
+                jcols = np.unique(jcols)
+        p = station_rays(rows, cols, o, scene, i0, i1, jcols, seed, s, sigma_mm)
+        if crop is not None:
+            m = ((p >= np.asarray(crop[0])) & (p <= np.asarray(crop[1]))).all(axis=1)
+            p = p[m]
+        parts.append(p)
     return np.concatenate(parts, axis=0)
 
 
-def config(idx: int, scale: float = 1.0, seed: int | None = None) -> Workload:
+# Half-width (mm) of the crop of the merged clouds: the box from -3 m to
+# +3 m around the first station in x and y, -1 m to 12 m in z, which holds
+# about 20M points of either merged cloud (the ground around the tripod,
+# densest near its foot, plus the sparse hits of the other stations).
+CROP_HALF_MM = 3000
+
+
+def crop_box(half_mm: int = CROP_HALF_MM) -> tuple:
+    return ((-half_mm, -half_mm, -1000), (half_mm, half_mm, 12000))
+
+
+def config(idx: int, scale: float = 1.0, seed: int | None = None, crop: bool = False) -> Workload:
     """Workload ``idx`` (1-5).  ``scale`` < 1 shrinks the ray grid (rows and
-    columns by sqrt(scale)) for quick tests; 1.0 is the stated size."""
+    columns by sqrt(scale)) for quick tests; 1.0 is the stated size.  For the
+    merged clouds (3, 5), ``crop`` gives only the points inside crop_box(),
+    re-indexed from 0 in their order in the whole cloud, with the keep ratio
+    of the whole."""
     def grid(r, c):
         f = math.sqrt(scale)
         return max(2, int(round(r * f))), max(2, int(round(c * f)))
@@ -239,17 +325,17 @@ def config(idx: int, scale: float = 1.0, seed: int | None = None) -> Workload:
         return Workload("scan-20M-k16-keep10", xyz, 16, n // 10)
     if idx == 3:
         r, c = grid(10000, 5000)
-        xyz = multi_station(10, r, c, 60, 400.0, 3 if seed is None else seed)
+        xyz = multi_station(10, r, c, 60, 400.0, 3 if seed is None else seed, crop=crop_box() if crop else None)
         n = xyz.shape[0]
-        return Workload("merged-10st-500M-k8-keep5", xyz, 8, n // 20)
+        return Workload("merged-10st-500M-k8-keep5" + ("/crop3m" if crop else ""), xyz, 8, n // 20)
     if idx == 4:
         return batch_config(4096 if scale >= 1.0 else max(2, int(4096 * scale)),
                             scale=1.0 if scale >= 1.0 else scale, base_seed=10000 if seed is None else seed)
     if idx == 5:
         r, c = grid(10000, 5000)
-        xyz = multi_station(40, r, c, 200, 1000.0, 5 if seed is None else seed)
+        xyz = multi_station(40, r, c, 200, 1000.0, 5 if seed is None else seed, crop=crop_box() if crop else None)
         n = xyz.shape[0]
-        return Workload("merged-40st-2B-k8-keep2", xyz, 8, n // 50)
+        return Workload("merged-40st-2B-k8-keep2" + ("/crop3m" if crop else ""), xyz, 8, n // 50)
     raise ValueError(idx)
 
 

@@ -22,11 +22,14 @@ from paper_2311_17604_amd import scangen  # noqa: E402
 
 OUT = os.path.join(HERE, "oracle_hashes.json")
 
-# name -> (workload index, scale); tests/test_gpu_golden.py repeats this table
+# name -> (workload index, scale, crop); tests/test_gpu_golden.py repeats
+# this table
 WORKLOADS = {
-    "scan-200k-k8-keep25": (1, 1.0),
-    "scan-20M-k16-keep10@0.25": (2, 0.25),
-    "scan-20M-k16-keep10": (2, 1.0),
+    "scan-200k-k8-keep25": (1, 1.0, False),
+    "scan-20M-k16-keep10@0.25": (2, 0.25, False),
+    "scan-20M-k16-keep10": (2, 1.0, False),
+    "merged-10st-500M-k8-keep5/crop3m": (3, 1.0, True),
+    "merged-40st-2B-k8-keep2/crop3m": (5, 1.0, True),
 }
 
 
@@ -35,13 +38,14 @@ def digest(a):
 
 
 def main(names):
-    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for name in names:
-        cfg, scale = WORKLOADS[name]
-        w = scangen.config(cfg, scale=scale)
+        cfg, scale, crop = WORKLOADS[name]
+        w = scangen.config(cfg, scale=scale, crop=crop)
         t = time.time()
         kept, order, oc = oracle.decimate(w.xyz, w.k, w.keep, b=8)
         dt = time.time() - t
+        # re-read: several runs may write their workloads concurrently
+        data = json.load(open(OUT)) if os.path.exists(OUT) else {}
         data[name] = {
             "n": int(len(w.xyz)), "k": w.k, "keep": int(w.keep),
             "kept_sha256": digest(kept.astype(np.int32)),

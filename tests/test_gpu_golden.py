@@ -21,11 +21,11 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 HASHES = os.path.join(HERE, "golden", "oracle_hashes.json")
-# name -> (workload index, scale), as in tests/golden/make_golden.py
+# name -> (workload index, scale, crop), as in tests/golden/make_golden.py
 WORKLOADS = {
-    "scan-200k-k8-keep25": (1, 1.0),
-    "scan-20M-k16-keep10@0.25": (2, 0.25),
-    "scan-20M-k16-keep10": (2, 1.0),
+    "scan-200k-k8-keep25": (1, 1.0, False),
+    "scan-20M-k16-keep10@0.25": (2, 0.25, False),
+    "scan-20M-k16-keep10": (2, 1.0, False),
 }
 
 
@@ -49,8 +49,8 @@ def test_golden_workload(gpu, name):
     import torch
     from paper_2311_17604_amd import pdd
     ref = json.load(open(HASHES))[name]
-    cfg, scale = WORKLOADS[name]
-    w = scangen.config(cfg, scale=scale)
+    cfg, scale, crop = WORKLOADS[name]
+    w = scangen.config(cfg, scale=scale, crop=crop)
     n = len(w.xyz)
     assert (n, w.k, w.keep) == (ref["n"], ref["k"], ref["keep"])
     x = torch.from_numpy(w.xyz).cuda()

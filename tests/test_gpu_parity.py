@@ -126,6 +126,18 @@ def test_decimate_scan(gpu, oracle_mod, scale, frac):
         assert np.array_equal(g, r), name
 
 
+@pytest.mark.parametrize("idx", [3, 5])
+def test_decimate_merged_crop(gpu, oracle_mod, idx):
+    # the crop of a merged multi-station cloud (uneven density: the ground
+    # around one tripod plus the sparse hits of the other stations) on a
+    # 1/100 ray grid, about 200k points
+    w = scangen.config(idx, scale=0.01, crop=True)
+    ref = oracle_mod.decimate(w.xyz, w.k, w.keep, b=6)
+    got = gpu_decimate(gpu, w.xyz, w.keep, w.k)
+    for g, r, name in zip(got, ref, ("kept", "order", "order_cost")):
+        assert np.array_equal(g, r), name
+
+
 def _dup_cloud(seed, n_base, box, sizes):
     """Random cloud plus groups of identical points (copies of random base
     points), shuffled so that each group's members interleave in index order."""

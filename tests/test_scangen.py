@@ -43,3 +43,35 @@ def test_batch_scan_shapes():
         r, c, ratio = scangen.batch_scan_shape(s)
         assert 0.1 <= ratio <= 0.5
         assert 5_000 <= r * c <= 2_100_000
+
+
+def test_merged_crop_equals_filtered_whole_cloud():
+    """A crop of a merged cloud casts only the rays that can reach the box,
+    and must give exactly the points of the whole cloud inside it, in the
+    same order (the range noise is counter-based per ray)."""
+    full = scangen.multi_station(4, 200, 300, 20, 200.0, 7)
+    for lo, hi in (((-15000, -10000, -1000), (20000, 25000, 12000)),   # holds the first station
+                   ((20000, -40000, -1000), (60000, 5000, 12000)),     # away from it
+                   ((-3000, -3000, -1000), (3000, 3000, 12000))):
+        m = ((full >= lo) & (full <= hi)).all(1)
+        cr = scangen.multi_station(4, 200, 300, 20, 200.0, 7, crop=(lo, hi))
+        assert m.sum() > 100
+        assert np.array_equal(full[m], cr)
+
+
+def test_ray_noise_counter_based():
+    rays = np.arange(200_000)
+    z = scangen.ray_noise(3, 2, rays, 2.0)
+    assert abs(z.mean()) < 0.02 and abs(z.std() - 2.0) < 0.02
+    sub = np.array([5, 77, 199_999, 1234])
+    assert np.array_equal(scangen.ray_noise(3, 2, sub, 2.0), z[sub])
+    assert not np.array_equal(scangen.ray_noise(3, 1, sub, 2.0), z[sub])
+    assert not np.array_equal(scangen.ray_noise(4, 2, sub, 2.0), z[sub])
+
+
+def test_merged_crop_workloads_small():
+    for idx in (3, 5):
+        w = scangen.config(idx, scale=0.0004, crop=True)
+        assert w.name.endswith("/crop3m") and len(w.xyz) > 0
+        assert ((w.xyz >= scangen.crop_box()[0]) & (w.xyz <= scangen.crop_box()[1])).all()
+        assert w.keep == len(w.xyz) // (20 if idx == 3 else 50)
