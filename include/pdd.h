@@ -180,7 +180,8 @@ int pdd_autotune(pdd_ctx *ctx, const int32_t *d_xyz, int64_t n, int64_t keep, co
 /* Counters of the last pdd_decimate on this context, written to stats[0..n),
  * n <= 14:
  *   0 rounds, 1 re-searches (buffer exhausted), 2 danger checks, 3 reverse-list
- *   rebuilds, 4 (unused, 0), 5 finest cell level (log2 mm), 6 list width used,
+ *   rebuilds, 4 device bytes the context's scratch pool holds after the call
+ *   (its high-water mark), 5 finest cell level (log2 mm), 6 list width used,
  *   7 touched (re-costed) points, 8 points tested by the initial k-NN search,
  *   9 lists certified in predicted regions, 10 lists in predicted regions
  *   that were not (searched again by the shell search), 11 points whose

@@ -214,6 +214,9 @@ int pdd::decimate_entry(Ctx* c, const int32_t* d_xyz, int64_t n, const int64_t* 
                            d_order, d_order_cost);
     }
     (void)hipStreamSynchronize(c->stream);
+    size_t held = 0;
+    for (const auto& buf : c->bufs) held += buf.bytes;
+    c->stats[4] = (int64_t)held;
     if (rc == PDD_OK && c->timing)
         for (int i = 1; i < pdd::kPhCount; i++) (void)hipEventElapsedTime(&c->phase_ms[i - 1], c->ev[i - 1], c->ev[i]);
     pdd::free_grid(&grid);

@@ -217,6 +217,7 @@ int hip_fail(Ctx* c, hipError_t e, const char* what);
 
 // scan / sort (scan_sort.hip)
 int exclusive_scan_u32(Ctx* c, const uint32_t* in, uint32_t* out, uint32_t count, uint32_t* total_dev);
+int exclusive_scan_u32_u64(Ctx* c, const uint32_t* in, uint64_t* out, uint32_t count);
 int radix_sort_pairs(Ctx* c, uint64_t* keys, uint32_t* vals, uint32_t n, int bits, uint64_t** keys_out,
                      uint32_t** vals_out);
 int fill_u32(Ctx* c, uint32_t* p, uint32_t value, size_t count);

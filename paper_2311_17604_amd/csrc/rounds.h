@@ -64,7 +64,7 @@ struct RoundArrays {
     uint64_t* ev_cost;
     int32_t* ev_orig;
     uint32_t* hist;      // [kSelBins0]
-    uint32_t* rev_off;   // [n+1]
+    uint64_t* rev_off;   // [n+1] (64-bit: n * K may pass 2^32)
     int32_t* rev_src;    // [n*K]
     int32_t* head;       // [n] pool chains
     int32_t* pool_src;

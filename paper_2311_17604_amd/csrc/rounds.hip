@@ -706,9 +706,9 @@ __global__ void __launch_bounds__(kBlock) rb_touch_recost(RoundArrays a) {
     for (uint32_t t = blockIdx.x * W + w; t < nR; t += nw) {
         const uint32_t x = a.R[t];
         // the CSR part, 64 entries at a time
-        const uint32_t e0 = a.rev_off[x], e1 = a.rev_off[x + 1];
-        for (uint32_t e = e0; e < e1; e += kWave) {
-            const bool valid = e + (uint32_t)lane < e1;
+        const uint64_t e0 = a.rev_off[x], e1 = a.rev_off[x + 1];
+        for (uint64_t e = e0; e < e1; e += kWave) {
+            const bool valid = e + (uint64_t)lane < e1;
             visit(valid, valid ? (uint32_t)a.rev_src[e + lane] : 0u);
         }
         // the appended chain: lane 0 walks up to 64 nodes, the lanes visit them
@@ -844,7 +844,7 @@ __global__ void rb_pool_end(RoundArrays a) {
 // entry is never removed again, so nothing needs to find it): one thread per
 // (point of the list L, entry).  fill = 0 counts, fill = 1 places.
 __global__ void __launch_bounds__(kBlock) rev_k(RoundArrays a, const uint32_t* __restrict__ L, uint32_t m,
-                                                uint32_t* cursor, int fill) {
+                                                uint32_t* deg, int fill) {
     const int K = a.K;
     const uint64_t total = (uint64_t)m * (uint64_t)K;
     for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
@@ -854,8 +854,8 @@ __global__ void __launch_bounds__(kBlock) rev_k(RoundArrays a, const uint32_t* _
         if (!a.alive[z] || j >= a.cnt[z]) continue;
         const uint32_t y = (uint32_t)a.nbr[(size_t)z * K + j];
         if (!a.alive[y]) continue;
-        if (fill) a.rev_src[atomicAdd(&cursor[y], 1u)] = (int32_t)z;
-        else atomicAdd(&cursor[y], 1u);
+        if (fill) a.rev_src[a.rev_off[y] + atomicAdd(&deg[y], 1u)] = (int32_t)z;
+        else atomicAdd(&deg[y], 1u);
     }
 }
 
@@ -1047,8 +1047,9 @@ int build_reverse(Ctx* c, RoundArrays& a, uint32_t n, const uint32_t* L, uint32_
     const unsigned gr = (unsigned)std::min<uint64_t>(((uint64_t)m * a.K + kBlock - 1) / kBlock, 16384u);
     hipLaunchKernelGGL(rev_k, dim3(std::max(gr, 1u)), dim3(kBlock), 0, c->stream, a, L, m, deg, 0);
     PDD_HIP(c, hipGetLastError());
-    if ((rc = exclusive_scan_u32(c, deg, a.rev_off, n + 1, nullptr))) return rc;
-    PDD_HIP(c, hipMemcpyAsync(deg, a.rev_off, (size_t)(n + 1) * 4, hipMemcpyDeviceToDevice, c->stream));
+    if ((rc = exclusive_scan_u32_u64(c, deg, a.rev_off, n + 1))) return rc;
+    // the fill pass counts again from zero within each point's run
+    if ((rc = fill_u32(c, deg, 0, n + 1))) return rc;
     hipLaunchKernelGGL(rev_k, dim3(std::max(gr, 1u)), dim3(kBlock), 0, c->stream, a, L, m, deg, 1);
     PDD_HIP(c, hipGetLastError());
     if ((rc = fill_u32(c, (uint32_t*)a.head, 0xFFFFFFFFu, n))) return rc;
@@ -1260,7 +1261,7 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, cons
     ALLOC(ev_cost, kSEvC, (size_t)n * 8);
     ALLOC(ev_orig, kSEvO, (size_t)n * 4);
     ALLOC(hist, kSHist, (size_t)kSelBins0 * 4);
-    ALLOC(rev_off, kSRevOff, (size_t)(n + 1) * 4);
+    ALLOC(rev_off, kSRevOff, (size_t)(n + 1) * 8);
     ALLOC(rev_src, kSRevSrc, (size_t)n * K * 4);
     ALLOC(head, kSHead, (size_t)n * 4);
     ALLOC(pool_src, kSPoolS, pool_cap * 4);
@@ -1321,7 +1322,7 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, cons
 
     KnnOut ko{a.nbr, a.cnt, a.cost, nullptr};
     mark(c, kPhGrid);
-    if ((rc = knn_all(c, g, k, K, ko, &c->stats[4]))) return rc;
+    if ((rc = knn_all(c, g, k, K, ko, nullptr))) return rc;
     mark(c, kPhKnn);
     if ((rc = build_reverse(c, a, n, a.alive_list[0], n))) return rc;
     mark(c, kPhReverse);

@@ -82,6 +82,79 @@ __global__ void __launch_bounds__(kBlock) scan_tiles(const uint32_t* __restrict_
     }
 }
 
+// 64-bit exclusive scan of 32-bit counts (sums that may pass 2^32): the
+// sum of each tile of kScanTile counts, one block's scan of the tile sums,
+// then the scan inside each tile on top of its tile's base.
+__device__ uint64_t block_exscan64(uint64_t v, uint64_t* total) {
+    __shared__ uint64_t wsum[kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    uint64_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)x, o, kWave);
+        const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(x >> 32), o, kWave);
+        if (lane >= o) x += ((uint64_t)hi << 32) | lo;
+    }
+    if (lane == kWave - 1) wsum[wid] = x;
+    __syncthreads();
+    uint64_t base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; w++) {
+        if (w < wid) base += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + x - v;
+}
+
+__global__ void __launch_bounds__(kBlock) scan64_partials(const uint32_t* __restrict__ in, uint32_t count,
+                                                          uint64_t* __restrict__ partial) {
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    uint64_t s = 0;
+    for (int i = 0; i < kScanIpt; i++) {
+        const uint64_t e = base + (uint64_t)i * kBlock + threadIdx.x;
+        if (e < count) s += in[e];
+    }
+    uint64_t tot;
+    block_exscan64(s, &tot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// one block: partial[0, nb) becomes its exclusive scan
+__global__ void __launch_bounds__(kBlock) scan64_bases(uint64_t* __restrict__ partial, uint32_t nb) {
+    uint64_t carry = 0;
+    for (uint32_t b0 = 0; b0 < nb; b0 += kBlock) {
+        const uint32_t i = b0 + threadIdx.x;
+        const uint64_t v = i < nb ? partial[i] : 0ull;
+        uint64_t tot;
+        const uint64_t ex = block_exscan64(v, &tot);
+        if (i < nb) partial[i] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) scan64_tiles(const uint32_t* __restrict__ in, uint64_t* __restrict__ out,
+                                                       uint32_t count, const uint64_t* __restrict__ base_ex) {
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    // each thread scans kScanIpt consecutive counts
+    const uint64_t e0 = base + (uint64_t)threadIdx.x * kScanIpt;
+    uint32_t v[kScanIpt];
+    uint64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanIpt; i++) {
+        v[i] = e0 + i < count ? in[e0 + i] : 0u;
+        s += v[i];
+    }
+    uint64_t tot;
+    uint64_t run = block_exscan64(s, &tot) + base_ex[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kScanIpt; i++) {
+        if (e0 + i < count) out[e0 + i] = run;
+        run += v[i];
+    }
+}
+
 __global__ void fill_u32_k(uint32_t* p, uint32_t v, size_t count) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -235,6 +308,20 @@ static int scan_level(Ctx* c, const uint32_t* in, uint32_t* out, uint32_t count,
 
 int exclusive_scan_u32(Ctx* c, const uint32_t* in, uint32_t* out, uint32_t count, uint32_t* total_dev) {
     return scan_level(c, in, out, count, total_dev, 0);
+}
+
+// out[i] = in[0] + ... + in[i-1] in 64 bits, for i < count.  Scratch slot 51
+// holds the tile sums.
+int exclusive_scan_u32_u64(Ctx* c, const uint32_t* in, uint64_t* out, uint32_t count) {
+    if (count == 0) return PDD_OK;
+    const uint32_t nb = (count + kScanTile - 1) / kScanTile;
+    uint64_t* part = (uint64_t*)scratch(c, 51, (size_t)nb * sizeof(uint64_t));
+    if (!part) return PDD_ENOMEM;
+    hipLaunchKernelGGL(scan64_partials, dim3(nb), dim3(kBlock), 0, c->stream, in, count, part);
+    hipLaunchKernelGGL(scan64_bases, dim3(1), dim3(kBlock), 0, c->stream, part, nb);
+    hipLaunchKernelGGL(scan64_tiles, dim3(nb), dim3(kBlock), 0, c->stream, in, out, count, part);
+    PDD_HIP(c, hipGetLastError());
+    return PDD_OK;
 }
 
 // Sorts by the low `bits` bits of the keys (stable).  The result lands in

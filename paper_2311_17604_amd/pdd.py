@@ -18,7 +18,7 @@ PDD_F_TIMING = 2
 PDD_F_PROGRESS = 4
 PHASES = ("grid", "knn", "reverse", "rounds", "final")
 
-STATS = ("rounds", "researches", "danger_checks", "reverse_rebuilds", "unused4", "voxel_log2",
+STATS = ("rounds", "researches", "danger_checks", "reverse_rebuilds", "scratch_bytes", "voxel_log2",
          "list_width", "touched", "knn_tested", "pred_hits", "pred_misses", "knn_fallbacks",
          "research_tested", "danger_enumerated")
 PRED_NPARAM = 8385

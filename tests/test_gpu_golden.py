@@ -74,3 +74,57 @@ def test_golden_workload(gpu, name):
     assert _sha(kept.astype(np.int32)) == ref["kept_sha256"], "kept"
     assert _sha(order.astype(np.int32)) == ref["order_sha256"], "order"
     assert _sha(oc.astype(np.uint64)) == ref["order_cost_sha256"], "order_cost"
+
+
+def test_merged_500M_full_size(gpu):
+    """The 500M-point merged cloud (10 stations, k=8, keep 5%) at its full
+    size, in the settings bench.py times for it (list width 16, round share
+    0.005).  The oracle's sequential run is out of reach at this size, so
+    the result is checked by properties that hold at any size, and by
+    brute-force recomputation on the CPU of sampled outputs: the removal
+    costs of sampled late removals (over the set alive at that moment, the
+    kept points and every later removal) and the final keys of sampled kept
+    points, which must all rank below the last removal's key."""
+    import torch
+    from oracle import oracle
+    from paper_2311_17604_amd import pdd
+    w = scangen.config(3)
+    n, k = len(w.xyz), w.k
+    assert n == 500_000_000
+    x = torch.from_numpy(w.xyz).cuda()
+    kept, order, oc = pdd.decimate(gpu, x, w.keep, k, b=8, round_frac=0.005)
+    gpu.stream.synchronize()
+    del x
+    kept = kept.cpu().numpy()
+    order = order.cpu().numpy()
+    oc = oc.cpu().numpy().view(np.uint64)
+    torch.cuda.empty_cache()
+    assert len(kept) == w.keep and len(order) == n - w.keep
+    assert np.all(np.diff(kept) > 0)
+    seen = np.zeros(n, np.uint8)
+    seen[kept] += 1
+    seen[order] += 1
+    assert np.all(seen == 1)
+    dec = (oc[1:] < oc[:-1]) | ((oc[1:] == oc[:-1]) & (order[1:] > order[:-1]))
+    assert np.all(dec), "removal keys must strictly decrease"
+    P = w.xyz
+    m = len(order)
+    tail = 2000  # the alive set at event t is the kept points plus order[t:]
+    S_idx = np.concatenate([kept, order[m - tail:]])
+    S = P[S_idx].astype(np.int64)
+
+    def cost_in(i, members, pts):
+        d2 = ((pts - P[i].astype(np.int64)) ** 2).sum(axis=1)
+        d2 = d2[members != i]
+        near = np.sort(np.partition(d2, k)[:k]) if len(d2) > k else np.sort(d2)
+        return sum(oracle.term(int(v)) for v in near)
+
+    rng = np.random.default_rng(3)
+    for t in sorted(rng.choice(np.arange(m - tail, m), 6, replace=False)) + [m - 1]:
+        live = np.concatenate([np.arange(len(kept)), len(kept) + np.arange(t - (m - tail), tail)])
+        assert cost_in(order[t], S_idx[live], S[live]) == int(oc[t]), "removal cost of event %d" % t
+    Kp = S[:len(kept)]
+    last_c, last_o = int(oc[-1]), int(order[-1])
+    for i in rng.choice(kept, 6, replace=False):
+        c = cost_in(i, kept, Kp)
+        assert c < last_c or (c == last_c and i > last_o), "kept point %d ranks above the last removal" % i
