@@ -26,6 +26,8 @@ WORKLOADS = {
     "scan-200k-k8-keep25": (1, 1.0, False),
     "scan-20M-k16-keep10@0.25": (2, 0.25, False),
     "scan-20M-k16-keep10": (2, 1.0, False),
+    "merged-10st-500M-k8-keep5/crop3m": (3, 1.0, True),
+    "merged-40st-2B-k8-keep2/crop3m": (5, 1.0, True),
 }
 
 
