@@ -99,6 +99,69 @@ __device__ inline uint64_t shfl_up64(uint64_t v) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+__device__ inline uint64_t shfl_xor64(uint64_t v, int m) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, kWave);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, kWave);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t shfl64(uint64_t v, int l) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, l, kWave);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), l, kWave);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// More candidates than this below the K-th distance in one batch are merged
+// into the list at once (wave_merge) instead of one by one.
+constexpr int kBulkInsert = 8;
+
+// Merges one candidate per lane (distance cd, ~0 for none, id cj) into the
+// wave's sorted list (lane j < K holds the j-th nearest, ~0 past the end):
+// a bitonic sort of the 64 candidates across the lanes, the elementwise
+// minimum of the list and the reversed candidates (the 64 smallest of both,
+// a bitonic sequence), then a bitonic merge.  Among equal distances the
+// choice is arbitrary, which leaves the list exact as a multiset.
+template <int K>
+__device__ inline void wave_merge(uint64_t cd, int32_t cj, uint64_t& my_d, int32_t& my_id) {
+    const int lane = (int)lane_id();
+#pragma unroll
+    for (int size = 2; size <= kWave; size <<= 1) {
+#pragma unroll
+        for (int stride = size / 2; stride > 0; stride >>= 1) {
+            const uint64_t od = shfl_xor64(cd, stride);
+            const int32_t oj = __shfl_xor(cj, stride, kWave);
+            const bool up = (lane & size) == 0 || size == kWave;
+            const bool lower = (lane & stride) == 0;
+            const bool take = (lower == up) ? od < cd : od > cd;
+            if (take) {
+                cd = od;
+                cj = oj;
+            }
+        }
+    }
+    const uint64_t rd = shfl64(cd, kWave - 1 - lane);
+    const int32_t rj = __shfl(cj, kWave - 1 - lane, kWave);
+    if (rd < my_d) {
+        my_d = rd;
+        my_id = rj;
+    }
+#pragma unroll
+    for (int stride = kWave / 2; stride > 0; stride >>= 1) {
+        const uint64_t od = shfl_xor64(my_d, stride);
+        const int32_t oj = __shfl_xor(my_id, stride, kWave);
+        const bool lower = (lane & stride) == 0;
+        const bool take = lower ? od < my_d : od > my_d;
+        if (take) {
+            my_d = od;
+            my_id = oj;
+        }
+    }
+    if (lane >= K) {
+        my_d = ~0ull;
+        my_id = -1;
+    }
+}
+
 __device__ inline void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -147,6 +210,10 @@ __device__ inline uint32_t wave_scan(const GridView& g, uint32_t q, int4 qp, con
         }
         uint64_t thr = readlane64(my_d, K - 1);
         uint64_t m = __ballot(d < thr);
+        if (__popcll(m) > kBulkInsert) {
+            wave_merge<K>(d < thr ? d : ~0ull, (int32_t)j, my_d, my_id);
+            m = 0;
+        }
         while (m) {
             const int l2 = __ffsll((unsigned long long)m) - 1;
             m &= m - 1;
