@@ -149,9 +149,14 @@ def main():
     ctx = pdd.Context(0)
     batch = w.offsets is not None
     tune = None
-    if not args.no_autotune and not batch:
+    if not args.no_autotune:
         t_tune = time.time()
-        tune = pdd.autotune(ctx, x, w.keep, w.k, b=args.b, voxel_log2=args.voxel_log2, round_frac=args.round_frac)
+        if batch:
+            tune = pdd.autotune_batch(ctx, x, w.offsets, w.keeps, w.k, b=args.b, voxel_log2=args.voxel_log2,
+                                      round_frac=args.round_frac)
+        else:
+            tune = pdd.autotune(ctx, x, w.keep, w.k, b=args.b, voxel_log2=args.voxel_log2,
+                                round_frac=args.round_frac)
         tune["tune_s"] = round(time.time() - t_tune, 2)
         print("autotune: %s" % tune, file=sys.stderr, flush=True)
         args.b, args.voxel_log2, args.round_frac = tune["b"], tune["voxel_log2"], tune["round_frac"]

@@ -177,6 +177,24 @@ int pdd_decimate_batch(pdd_ctx *ctx, const int32_t *d_xyz, const int64_t *h_offs
 int pdd_autotune(pdd_ctx *ctx, const int32_t *d_xyz, int64_t n, int64_t keep, const pdd_opts *base,
                  int64_t sample, pdd_opts *out, float *best_ms);
 
+/*
+ * Autotuner for pdd_decimate_batch: chooses round_frac and b for this batch
+ * by timing trial batched decimations of every step-th cloud (whole clouds,
+ * about `sample` points in all; 0 = 8M), gathered into one smaller batch:
+ * round share, then list width.  The finest level stays automatic.  Like
+ * pdd_autotune, the choice changes only the time of the result, never the
+ * result (the question of voxel and buffer sizes that Sec. 7 leaves open).
+ *   d_xyz, h_offsets, nscan, h_keep : the batch, as for pdd_decimate_batch
+ *   base    : k and point_stride used; other fields are the starting point
+ *   out     : receives base with the chosen b and round_frac
+ *   best_ms : (if not NULL) the best trial's time on the sample
+ * Synchronises the stream.  Errors: PDD_EINVAL, PDD_ERANGE, PDD_ENOMEM,
+ * PDD_EHIP, PDD_EINTERNAL.
+ */
+int pdd_autotune_batch(pdd_ctx *ctx, const int32_t *d_xyz, const int64_t *h_offsets, int32_t nscan,
+                       const int64_t *h_keep, const pdd_opts *base, int64_t sample, pdd_opts *out,
+                       float *best_ms);
+
 /* Counters of the last pdd_decimate on this context, written to stats[0..n),
  * n <= 14:
  *   0 rounds, 1 re-searches (buffer exhausted), 2 danger checks, 3 reverse-list

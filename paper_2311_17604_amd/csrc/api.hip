@@ -169,6 +169,8 @@ constexpr int64_t kBatchGroup = (int64_t)1 << 28;
 }  // extern "C"
 
 namespace pdd {
+int autotune_batch(Ctx* c, const int32_t* d_xyz, const int64_t* h_off, int nscan, const int64_t* h_keep,
+                   const pdd_opts* base, int64_t sample, pdd_opts* out, float* best_ms);
 int decimate_entry(Ctx* c, const int32_t* d_xyz, int64_t n, const int64_t* h_off, const int64_t* h_keep, int nseg,
                    const pdd_opts* opts, int32_t* d_kept, int32_t* d_order, uint64_t* d_order_cost);
 int autotune(Ctx* c, const int32_t* d_xyz, int64_t n, int64_t keep, const pdd_opts* base, int64_t sample,
@@ -292,6 +294,16 @@ int pdd_autotune(pdd_ctx* ctx, const int32_t* d_xyz, int64_t n, int64_t keep, co
     Ctx* c = &ctx->c;
     if (hipSetDevice(c->device) != hipSuccess) return PDD_EHIP;
     return pdd::autotune(c, d_xyz, n, keep, base, sample, out, best_ms);
+}
+
+int pdd_autotune_batch(pdd_ctx* ctx, const int32_t* d_xyz, const int64_t* h_offsets, int32_t nscan,
+                       const int64_t* h_keep, const pdd_opts* base, int64_t sample, pdd_opts* out, float* best_ms) {
+    if (!ctx || !d_xyz || !h_offsets || !h_keep || !base || !out || nscan < 1 || nscan > (1 << 20))
+        return PDD_EINVAL;
+    if (h_offsets[0] != 0) return PDD_EINVAL;
+    Ctx* c = &ctx->c;
+    if (hipSetDevice(c->device) != hipSuccess) return PDD_EHIP;
+    return pdd::autotune_batch(c, d_xyz, h_offsets, nscan, h_keep, base, sample, out, best_ms);
 }
 
 // ---------------------------------------------------------------------------

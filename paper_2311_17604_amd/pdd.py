@@ -66,6 +66,9 @@ def load():
     lib.pdd_autotune.argtypes = [P, P, i64, i64, ctypes.POINTER(Opts), i64, ctypes.POINTER(Opts),
                                  ctypes.POINTER(ctypes.c_float)]
     lib.pdd_autotune.restype = ctypes.c_int
+    lib.pdd_autotune_batch.argtypes = [P, P, P, i32, P, ctypes.POINTER(Opts), i64, ctypes.POINTER(Opts),
+                                       ctypes.POINTER(ctypes.c_float)]
+    lib.pdd_autotune_batch.restype = ctypes.c_int
     lib.pdd_last_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.c_int]
     lib.pdd_last_stats.restype = ctypes.c_int
     lib.pdd_last_timing.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
@@ -209,6 +212,27 @@ def autotune(ctx: Context, xyz, keep: int, k: int, sample: int = 0, b: int = 0, 
     ms = ctypes.c_float()
     ctx._check(ctx.lib.pdd_autotune(ctx.h, _ptr(pts), pts.shape[0], keep, ctypes.byref(base), sample,
                                     ctypes.byref(out), ctypes.byref(ms)), "pdd_autotune")
+    return {"b": int(out.b), "voxel_log2": int(out.voxel_log2), "round_frac": float(out.round_frac),
+            "best_ms": float(ms.value)}
+
+
+def autotune_batch(ctx: Context, xyz, offsets, keeps, k: int, sample: int = 0, b: int = 0, voxel_log2: int = 0,
+                   round_frac: float = 0.0):
+    """Chosen settings for decimate_batch on this batch: dict(b, voxel_log2,
+    round_frac, best_ms) from timed trials on every step-th cloud (results
+    never depend on them)."""
+    import numpy as np
+    pts, stride = _points(xyz)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    kp = np.ascontiguousarray(keeps, dtype=np.int64)
+    if off.shape != (len(kp) + 1,) or off[-1] != pts.shape[0]:
+        raise ValueError("offsets must have len(keeps) + 1 entries ending at the number of points")
+    base = Opts(k=k, b=b, voxel_log2=voxel_log2, round_frac=round_frac, point_stride=stride, flags=0)
+    out = Opts()
+    ms = ctypes.c_float()
+    ctx._check(ctx.lib.pdd_autotune_batch(ctx.h, _ptr(pts), off.ctypes.data_as(ctypes.c_void_p), len(kp),
+                                          kp.ctypes.data_as(ctypes.c_void_p), ctypes.byref(base), sample,
+                                          ctypes.byref(out), ctypes.byref(ms)), "pdd_autotune_batch")
     return {"b": int(out.b), "voxel_log2": int(out.voxel_log2), "round_frac": float(out.round_frac),
             "best_ms": float(ms.value)}
 

@@ -38,3 +38,28 @@ def test_autotune_settings_keep_result(gpu, oracle_mod):
         if name == "order_cost":
             a_, b_ = a_.view(np.uint64), b_.view(np.uint64)
         assert np.array_equal(a_, b_) and np.array_equal(a_, r_), name
+
+
+def test_autotune_batch_settings_keep_result(gpu, oracle_mod):
+    # 24 scans of the batch generator at 1/400 size; the tuner samples every
+    # few scans, and the batch decimated with its choice equals the oracle
+    # run on each scan alone
+    import torch
+    from paper_2311_17604_amd import pdd
+    w = scangen.batch_config(24, scale=1 / 400, base_seed=10000)
+    x = torch.from_numpy(w.xyz).cuda()
+    t = pdd.autotune_batch(gpu, x, w.offsets, w.keeps, w.k, sample=20000)
+    assert t["b"] in (0, 4, 16, 24) and 0 < t["round_frac"] <= 0.02
+    assert t["voxel_log2"] == 0 and t["best_ms"] > 0
+    kept, order, oc = pdd.decimate_batch(gpu, x, w.offsets, w.keeps, w.k, b=t["b"], round_frac=t["round_frac"])
+    gpu.stream.synchronize()
+    kept, order, oc = kept.cpu().numpy(), order.cpu().numpy(), oc.cpu().numpy().view(np.uint64)
+    ko = np.concatenate([[0], np.cumsum(w.keeps)])
+    sizes = np.diff(w.offsets)
+    ro = np.concatenate([[0], np.cumsum(sizes - w.keeps)])
+    for s in range(len(w.keeps)):
+        P = w.xyz[w.offsets[s]:w.offsets[s + 1]]
+        ref = oracle_mod.decimate(P, w.k, int(w.keeps[s]), b=6)
+        assert np.array_equal(kept[ko[s]:ko[s + 1]], ref[0]), ("kept", s)
+        assert np.array_equal(order[ro[s]:ro[s + 1]], ref[1]), ("order", s)
+        assert np.array_equal(oc[ro[s]:ro[s + 1]], ref[2]), ("order_cost", s)
