@@ -72,7 +72,7 @@ int autotune(Ctx* c, const int32_t* d_xyz, int64_t n, int64_t keep, const pdd_op
     const int s_auto_sample = (int)c->stats[5];
     int dvox = 0;
     // coordinate descent: round share, list width, finest level
-    for (float f : {0.005f, 0.0025f, 0.02f, 0.04f}) {
+    for (float f : {0.005f, 0.0025f, 0.00125f, 0.02f, 0.04f}) {
         pdd_opts o = best;
         o.round_frac = f;
         float ms;
@@ -181,7 +181,7 @@ int autotune_batch(Ctx* c, const int32_t* d_xyz, const int64_t* h_off, int nscan
     if (best.round_frac == 0.0f) best.round_frac = 0.01f;
     float tbest = 0.f;
     int rc = trial(best, &tbest);
-    for (float f : {0.005f, 0.0025f, 0.00125f, 0.02f}) {
+    for (float f : {0.005f, 0.0025f, 0.00125f, 0.000625f, 0.02f}) {
         pdd_opts o = best;
         o.round_frac = f;
         float ms;
