@@ -766,7 +766,15 @@ __global__ void __launch_bounds__(kBlock) rb_research(RoundArrays a, GridView g)
         SearchCtx sc{a.alive};
         uint64_t d;
         int32_t id;
-        const int L0 = start_level(g, z, K + 1, a.cell_alive);
+        // z's list was full (a re-search follows only a full list), and its
+        // K-th distance can only have grown since: start at the finest level
+        // whose cell edge reaches the old K-th distance
+        const int32_t last = a.nbr[(size_t)z * K + K - 1];
+        const int4 pl = a.pts[(uint32_t)last];
+        const uint64_t dold = dist2(pz.x, pz.y, pz.z, pl.x, pl.y, pl.z);
+        int sn = 0;
+        while (sn < 21 && (1ull << (2 * sn)) < dold) sn++;
+        const int L0 = min(max(sn - g.lv[0].s, 0), g.nlev - 1);
         wave_knn<K, kAlive>(g, z, pz, sc, K, L0, d, id, lds[w][0], lds[w][1], &tested);
         const int c = __popcll(__ballot(lane < K && d != ~0ull));
         const int use = c < k ? c : k;
