@@ -205,14 +205,16 @@ int pdd_autotune_batch(pdd_ctx *ctx, const int32_t *d_xyz, const int64_t *h_offs
  *   that were not (searched again by the shell search), 11 points whose
  *   tile could not certify their list (all searched again), 12 points tested
  *   by the re-searches, 13 survivors enumerated by the danger checks.
- * Entries 8-10 are also written by pdd_knn_cost.
+ * Entries 8-10 are also written by pdd_knn_cost.  After pdd_decimate_batch
+ * the counters are summed over its groups of clouds (4-6: the last group's).
  * Returns the number of counters written. */
 int pdd_last_stats(const pdd_ctx *ctx, int64_t *stats, int n);
 
 /* Phase durations in ms of the last pdd_decimate on this context that ran
  * with PDD_F_TIMING, from HIP events recorded on the context's stream,
  * written to ms[0..n): 0 grid build, 1 initial k-NN cost kernel, 2 reverse
- * lists, 3 removal rounds, 4 finalisation (kept set and removal order).
+ * lists, 3 removal rounds, 4 finalisation (kept set and removal order);
+ * after pdd_decimate_batch, summed over its groups of clouds.
  * Returns the number written. */
 int pdd_last_timing(const pdd_ctx *ctx, float *ms, int n);
 

@@ -251,6 +251,10 @@ int pdd_decimate_batch(pdd_ctx* ctx, const int32_t* d_xyz, const int64_t* h_offs
     // segmented decimation; the outputs of a group go after the previous ones
     int64_t kept_at = 0, order_at = 0;
     int first = 0;
+    // counters and phase times of the whole call: summed over the groups
+    // (scratch held and the levels/list width: the last group's)
+    int64_t stats[pdd::kNumStats] = {0};
+    float phase[pdd::kPhCount] = {0};
     while (first < nscan) {
         int last = first + 1;
         while (last < nscan && h_offsets[last + 1] - h_offsets[first] <= kBatchGroup) last++;
@@ -267,10 +271,14 @@ int pdd_decimate_batch(pdd_ctx* ctx, const int32_t* d_xyz, const int64_t* h_offs
         int rc = decimate_common(ctx, xyz, off[ng], off.data(), keep.data(), ng, opts, d_kept + kept_at,
                                  d_order ? d_order + order_at : nullptr, d_order_cost ? d_order_cost + order_at : nullptr);
         if (rc) return rc;
+        for (int i = 0; i < pdd::kNumStats; i++) stats[i] = (i == 4 || i == 5 || i == 6) ? ctx->c.stats[i] : stats[i] + ctx->c.stats[i];
+        for (int i = 0; i < pdd::kPhCount; i++) phase[i] += ctx->c.phase_ms[i];
         kept_at += gkeep;
         order_at += off[ng] - gkeep;
         first = last;
     }
+    for (int i = 0; i < pdd::kNumStats; i++) ctx->c.stats[i] = stats[i];
+    for (int i = 0; i < pdd::kPhCount; i++) ctx->c.phase_ms[i] = phase[i];
     return PDD_OK;
 }
 
