@@ -81,6 +81,7 @@ __global__ void rb_begin(RoundArrays a) {
                 st->nA = st->nCand = st->nDanger = st->nSurv = st->nTouch = st->nResearch = st->nR = 0;
                 st->mode = 0;
                 st->nOvf = 0;
+                st->nA2 = 0;
                 st->work = 0;
                 for (int j = 0; j < kLev; j++) st->surv_min[j] = ~0ull;
                 st->full = st->p_valid ? 0u : 1u;
@@ -523,14 +524,13 @@ __global__ void __launch_bounds__(kBlock) ovf_compact_k(RoundArrays a) {
     }
 }
 
+// (nA2 is cleared by rb_begin: a block of this kernel that cleared it could
+// run before another block has read it)
 __global__ void __launch_bounds__(kBlock) ovf_copy_k(RoundArrays a) {
     RoundDev* st = a.st;
     const uint32_t m = st->nA2;
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) a.A[t] = a.cand[1][t];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->nA = m;
-        st->nA2 = 0;
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->nA = m;
 }
 
 // ---------------------------------------------------------------------------

@@ -91,3 +91,20 @@ def test_batch_identical_groups_and_tiny(gpu, oracle_mod):
     keeps.append(1)
     got = _run_batch(gpu, clouds, keeps, 8)
     _check_against_oracle(oracle_mod, clouds, keeps, 8, got)
+
+
+def test_batch_budget_cut_repeated(gpu, oracle_mod):
+    # rounds whose A holds more than some clouds' remaining budget go
+    # through the per-cloud budget cut (a segmented sort and compaction of
+    # A); a large round share makes that happen in most rounds.  Repeated
+    # on one context: the compacted A's length once came from a counter that
+    # one block of the copy kernel could clear before another had read it.
+    rng = np.random.default_rng(11)
+    clouds, keeps = [], []
+    for s in range(40):
+        n = int(rng.integers(30, 900))
+        clouds.append(scangen.random_cloud(n, int(rng.choice([3, 50, 2000])), int(rng.integers(0, 1 << 30))))
+        keeps.append(int(rng.integers(1, max(2, n // 8))))
+    for _ in range(4):
+        got = _run_batch(gpu, clouds, keeps, 4, round_frac=0.3, check=True)
+        _check_against_oracle(oracle_mod, clouds, keeps, 4, got)
