@@ -630,9 +630,13 @@ __global__ void rb_remove_end(RoundArrays a) {
     else if (yield > 0.2f && st->work < (1u << 20)) st->frac = fminf(st->frac * 1.5f, st->frac_max);
 }
 
+// removed points per wavefront in rb_touch_recost, and chain nodes each of
+// them collects per step (kTouchGroup * kChainStep = one wavefront)
+constexpr int kTouchGroup = 4, kChainStep = kWave / kTouchGroup;
+
 // Re-costs every alive point whose list held a removed point (the removed
-// points' reverse lists): one wavefront per removed point, one lane per
-// reverse entry.  The lane that touches a point first this round re-costs
+// points' reverse lists): kTouchGroup removed points per wavefront, one lane
+// per reverse entry.  The lane that touches a point first this round re-costs
 // it from its list's first k alive entries; a list with fewer alive entries
 // than k that did not hold every alive point is queued for the re-search
 // (staged in the wave's LDS: one shared-counter atomic per 64 entries).
@@ -702,29 +706,57 @@ __global__ void __launch_bounds__(kBlock) rb_touch_recost(RoundArrays a) {
             wave_sync_lds();
         }
     };
+    // kTouchGroup removed points per wave: their CSR entries packed into
+    // chunks of 64, their chains walked side by side
     const uint32_t nw = gridDim.x * W;
-    for (uint32_t t = blockIdx.x * W + w; t < nR; t += nw) {
-        const uint32_t x = a.R[t];
-        // the CSR part, 64 entries at a time
-        const uint64_t e0 = a.rev_off[x], e1 = a.rev_off[x + 1];
-        for (uint64_t e = e0; e < e1; e += kWave) {
-            const bool valid = e + (uint64_t)lane < e1;
-            visit(valid, valid ? (uint32_t)a.rev_src[e + lane] : 0u);
+    for (uint32_t g0 = (blockIdx.x * W + w) * kTouchGroup; g0 < nR; g0 += nw * kTouchGroup) {
+        const bool mine = lane < kTouchGroup && g0 + (uint32_t)lane < nR;
+        const uint32_t x = mine ? a.R[g0 + lane] : 0u;
+        const uint64_t e0 = mine ? a.rev_off[x] : 0ull;
+        const uint32_t len = mine ? (uint32_t)(a.rev_off[x + 1] - e0) : 0u;
+        // exclusive prefix of the lengths over the group's lanes
+        uint32_t incl = len;
+#pragma unroll
+        for (int o = 1; o < kTouchGroup; o <<= 1) {
+            const uint32_t v = (uint32_t)__shfl_up((int)incl, o, kWave);
+            if (lane >= o) incl += v;
         }
-        // the appended chain: lane 0 walks up to 64 nodes, the lanes visit them
-        int32_t p = a.head[x];
-        while (p >= 0) {
+        uint32_t ex[kTouchGroup];
+        uint64_t st0[kTouchGroup];
+#pragma unroll
+        for (int i = 0; i < kTouchGroup; i++) {
+            ex[i] = (uint32_t)__shfl((int)(incl - len), i, kWave);
+            st0[i] = readlane64(e0, i);
+        }
+        const uint32_t total = (uint32_t)__shfl((int)incl, kTouchGroup - 1, kWave);
+        for (uint32_t c0 = 0; c0 < total; c0 += kWave) {
+            const uint32_t u = c0 + (uint32_t)lane;
+            const bool valid = u < total;
+            int i = 0;
+#pragma unroll
+            for (int j = 1; j < kTouchGroup; j++)
+                if (u >= ex[j]) i = j;
+            uint64_t src = st0[0] + u;
+#pragma unroll
+            for (int j = 1; j < kTouchGroup; j++)
+                if (i == j) src = st0[j] + (u - ex[j]);
+            visit(valid, valid ? (uint32_t)a.rev_src[src] : 0u);
+        }
+        // the appended chains: lane j < kTouchGroup walks up to kChainStep
+        // nodes of its point's chain into its LDS segment, then the lanes
+        // visit the collected nodes
+        int32_t p = mine ? a.head[x] : -1;
+        while (__any(p >= 0)) {
             uint32_t m = 0;
-            if (lane == 0) {
-                while (p >= 0 && m < (uint32_t)kWave) {
-                    s_chain[w][m++] = (uint32_t)a.pool_src[p];
+            if (lane < kTouchGroup) {
+                while (p >= 0 && m < (uint32_t)kChainStep) {
+                    s_chain[w][lane * kChainStep + m++] = (uint32_t)a.pool_src[p];
                     p = a.pool_next[p];
                 }
             }
-            m = (uint32_t)__shfl((int)m, 0, kWave);
-            p = __shfl(p, 0, kWave);
+            const uint32_t mj = (uint32_t)__shfl((int)m, lane / kChainStep, kWave);
             wave_sync_lds();
-            const bool valid = (uint32_t)lane < m;
+            const bool valid = (uint32_t)(lane % kChainStep) < mj;
             visit(valid, valid ? s_chain[w][lane] : 0u);
             wave_sync_lds();
         }
