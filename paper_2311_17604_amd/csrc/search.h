@@ -59,15 +59,6 @@ __device__ inline void anchor_cell(const GridView& g, uint32_t j, uint32_t need,
     *cout = c;
 }
 
-// Level at which a search around sorted point j starts: one below its anchor
-// level, so that the 3x3x3 block there usually holds the neighbourhood.
-__device__ inline int start_level(const GridView& g, uint32_t j, uint32_t need, const uint32_t* alive_cnt) {
-    int L;
-    uint32_t c;
-    anchor_cell(g, j, need, alive_cnt, &L, &c);
-    return L > 0 ? L - 1 : 0;
-}
-
 // ---------------------------------------------------------------------------
 // One wavefront per query.  The search starts at level L0 and grows the
 // block of cells around the query one shell at a time: shells 0 and 1 at
