@@ -17,6 +17,10 @@ line with
                 matches the workload, list width and kernel source;
   cpu_baseline  the CPU oracle (one core) on a bounded window of the same
                 scan.
+config.plain holds the same steps without the learned search region, and
+config.batched the batch workload at 1/16 size (256 scans): one autotuned
+pdd_decimate_batch per step against the same scans one pdd_decimate at a
+time, with the kept sets compared.
 """
 from __future__ import annotations
 
@@ -76,6 +80,47 @@ def cpu_baseline(w, rows_cols):
 
 
 GRIDS = {1: (500, 400), 2: (5000, 4000)}
+BATCH_SCALE = 0.0625  # the batch workload beside the single-scan line: 256 scans, 1/16 sizes
+
+
+def batch_compare(ctx, steps, warmup, learned):
+    """The batch workload at 1/16 size (256 scans of 625 to 125k points):
+    one autotuned pdd_decimate_batch per step (with the learned search region
+    when `learned`) against the same scans decimated one pdd_decimate at a
+    time (library defaults, plain), with the kept sets compared."""
+    import numpy as np
+    import torch
+
+    from paper_2311_17604_amd import pdd, scangen
+    w = scangen.config(4, scale=BATCH_SCALE)
+    x = torch.from_numpy(w.xyz).cuda()
+    n = len(w.xyz)
+    tune = pdd.autotune_batch(ctx, x, w.offsets, w.keeps, w.k)
+    kw = dict(b=tune["b"], voxel_log2=tune["voxel_log2"], round_frac=tune["round_frac"])
+    for _ in range(warmup):
+        pdd.decimate_batch(ctx, x, w.offsets, w.keeps, w.k, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        kb, _, _ = pdd.decimate_batch(ctx, x, w.offsets, w.keeps, w.k, **kw)
+    torch.cuda.synchronize()
+    dtb = time.perf_counter() - t0
+    if learned:
+        pdd.pred_enable(ctx, False)
+    parts = []
+    t0 = time.perf_counter()
+    for s in range(len(w.keeps)):
+        a, b = int(w.offsets[s]), int(w.offsets[s + 1])
+        k1, _, _ = pdd.decimate(ctx, x[a:b].contiguous(), int(w.keeps[s]), w.k)
+        parts.append(k1)
+    torch.cuda.synchronize()
+    dt1 = time.perf_counter() - t0
+    if learned:
+        pdd.pred_enable(ctx, True, PRED_MARGIN)
+    same = bool(np.array_equal(torch.cat(parts).cpu().numpy(), kb.cpu().numpy()))
+    return {"workload": "%s@%g" % (w.name, BATCH_SCALE), "n": n, "clouds": int(len(w.keeps)),
+            "value": n * steps / dtb, "ms_per_step": dtb * 1e3 / steps, "learned": learned, "autotune": tune,
+            "one_by_one": {"value": n / dt1, "ms": dt1 * 1e3}, "same_kept": same}
 PRED_MARGIN = 0.25
 
 
@@ -119,6 +164,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true",
                     help="do not also time the plain configuration (no predictor) for comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="do not also time the batch workload (256 scans at 1/16 size, batched vs one at a time)")
     ap.add_argument("--quiet", action="store_true", help="no per-50-round progress lines from the library")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run four 1 GiB device-to-device copies (scales the HBM byte counters)")
@@ -216,6 +263,11 @@ def main():
             "kernel": kname, "algorithmic_bytes_per_launch": algo,
             "bytes_per_point": bytes_per_point, "avg_launch_ms": knn_ms}
 
+    batched = None
+    if not args.no_batch and not batch:
+        print("batch workload: batched vs one at a time", file=sys.stderr, flush=True)
+        batched = batch_compare(ctx, args.steps, args.warmup, pred is not None)
+
     cpu = None
     if not args.no_cpu_baseline and args.config in GRIDS and args.scale == 1.0:
         print("cpu baseline: oracle on a window of the scan", file=sys.stderr, flush=True)
@@ -238,7 +290,7 @@ def main():
                    "method": "+".join([m for m, on in (("batched", batch), ("autotuned", tune is not None),
                                                         ("learned", pred is not None)) if on]) or "plain",
                    "clouds": int(len(w.keeps)) if batch else 1, "autotune": tune, "predictor": pred,
-                   "plain": plain,
+                   "plain": plain, "batched": batched,
                    "gen_s": round(t_gen, 2), "stats": st, "phase_ms": ph},
         "roofline": roof,
         "cpu_baseline": cpu,
