@@ -195,6 +195,43 @@ int pdd_autotune_batch(pdd_ctx *ctx, const int32_t *d_xyz, const int64_t *h_offs
                        const int64_t *h_keep, const pdd_opts *base, int64_t sample, pdd_opts *out,
                        float *best_ms);
 
+/*
+ * Quality of a (decimated) cloud, the measures of Sec. 6: for every point
+ * the number of other points within each of R radii, exact in integers
+ * (|p - q|^2 <= r2[r] on int32 millimetres); per radius their mean and the
+ * fractiles 0.01, 0.1, 0.25, 0.5, 0.75, 0.9, 0.99 (element of rank
+ * floor(q (m - 1)) in ascending order); the least-squares line of count
+ * against neighbourhood area (pi r^2 in m^2) over all (point, radius) pairs,
+ * whose slope estimates the density, with its R^2 and RMSE, computed in
+ * double from the exact sums; and the squared distance from every point to
+ * its nearest other point, whose minimum Eq. 2 maximises.
+ *   d_xyz        : [m] points, int32 x, y, z (12 bytes) or x, y, z, pad (16)
+ *   h_r2         : host array of R squared radii (mm^2), strictly increasing,
+ *                  1 <= R <= PDD_QUALITY_MAX_R
+ *   d_counts     : [m * R] uint32 or NULL: counts, point-major
+ *   d_nn2        : [m] int64 or NULL: squared nearest-neighbour distances
+ *   out          : host; receives the summary
+ * m >= 2.  Synchronises the stream.  Errors: PDD_EINVAL (also when the
+ * largest radius exceeds what the grid's levels cover), PDD_ERANGE,
+ * PDD_ENOMEM, PDD_EHIP.
+ */
+#define PDD_QUALITY_MAX_R 32
+#define PDD_QUALITY_NFRAC 7
+typedef struct {
+    int32_t R;
+    int32_t fractile_capped;                       /* 1 if a fractile reached the 4095 cap */
+    int64_t m;
+    double area_m2[PDD_QUALITY_MAX_R];
+    double mean[PDD_QUALITY_MAX_R];
+    uint32_t fractile[PDD_QUALITY_MAX_R][PDD_QUALITY_NFRAC];
+    uint64_t sum[PDD_QUALITY_MAX_R];               /* exact sum of the counts per radius */
+    uint64_t sum_sq[PDD_QUALITY_MAX_R];            /* exact sum of their squares */
+    double slope, intercept, r_squared, rmse;      /* count = intercept + slope * area */
+    int64_t nn2_min;                               /* smallest squared nearest-neighbour distance */
+} pdd_quality;
+int pdd_quality_measure(pdd_ctx *ctx, const int32_t *d_xyz, int64_t m, int32_t stride_bytes, const int64_t *h_r2,
+                        int32_t R, uint32_t *d_counts, int64_t *d_nn2, pdd_quality *out);
+
 /* Counters of the last pdd_decimate on this context, written to stats[0..n),
  * n <= 14:
  *   0 rounds, 1 re-searches (buffer exhausted), 2 danger checks, 3 reverse-list

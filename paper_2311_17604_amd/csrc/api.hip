@@ -169,6 +169,8 @@ constexpr int64_t kBatchGroup = (int64_t)1 << 28;
 }  // extern "C"
 
 namespace pdd {
+int quality(Ctx* c, const int32_t* d_xyz, int64_t m, int stride, const int64_t* h_r2, int R, uint32_t* d_counts,
+            int64_t* d_nn2, pdd_quality* out);
 int autotune_batch(Ctx* c, const int32_t* d_xyz, const int64_t* h_off, int nscan, const int64_t* h_keep,
                    const pdd_opts* base, int64_t sample, pdd_opts* out, float* best_ms);
 int decimate_entry(Ctx* c, const int32_t* d_xyz, int64_t n, const int64_t* h_off, const int64_t* h_keep, int nseg,
@@ -302,6 +304,14 @@ int pdd_autotune(pdd_ctx* ctx, const int32_t* d_xyz, int64_t n, int64_t keep, co
     Ctx* c = &ctx->c;
     if (hipSetDevice(c->device) != hipSuccess) return PDD_EHIP;
     return pdd::autotune(c, d_xyz, n, keep, base, sample, out, best_ms);
+}
+
+int pdd_quality_measure(pdd_ctx* ctx, const int32_t* d_xyz, int64_t m, int32_t stride_bytes, const int64_t* h_r2,
+                        int32_t R, uint32_t* d_counts, int64_t* d_nn2, pdd_quality* out) {
+    if (!ctx || !d_xyz || !h_r2 || !out || m < 2 || m >= (int64_t)0x7FFFFFFF) return PDD_EINVAL;
+    Ctx* c = &ctx->c;
+    if (hipSetDevice(c->device) != hipSuccess) return PDD_EHIP;
+    return pdd::quality(c, d_xyz, m, stride_bytes == 0 ? 12 : stride_bytes, h_r2, R, d_counts, d_nn2, out);
 }
 
 int pdd_autotune_batch(pdd_ctx* ctx, const int32_t* d_xyz, const int64_t* h_offsets, int32_t nscan,

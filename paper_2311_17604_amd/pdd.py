@@ -38,6 +38,18 @@ class Opts(ctypes.Structure):
                 ("round_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
+QMAX_R, QNFRAC = 32, 7
+QFRACTILES = (0.01, 0.1, 0.25, 0.5, 0.75, 0.9, 0.99)
+
+
+class Quality(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_int32), ("fractile_capped", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("area_m2", ctypes.c_double * QMAX_R), ("mean", ctypes.c_double * QMAX_R),
+                ("fractile", (ctypes.c_uint32 * QNFRAC) * QMAX_R), ("sum", ctypes.c_uint64 * QMAX_R),
+                ("sum_sq", ctypes.c_uint64 * QMAX_R), ("slope", ctypes.c_double), ("intercept", ctypes.c_double),
+                ("r_squared", ctypes.c_double), ("rmse", ctypes.c_double), ("nn2_min", ctypes.c_int64)]
+
+
 def load():
     """Load libpdd.so (raises if it is missing: there is no fallback)."""
     global _lib
@@ -69,6 +81,8 @@ def load():
     lib.pdd_autotune_batch.argtypes = [P, P, P, i32, P, ctypes.POINTER(Opts), i64, ctypes.POINTER(Opts),
                                        ctypes.POINTER(ctypes.c_float)]
     lib.pdd_autotune_batch.restype = ctypes.c_int
+    lib.pdd_quality_measure.argtypes = [P, P, i64, i32, P, i32, P, P, ctypes.POINTER(Quality)]
+    lib.pdd_quality_measure.restype = ctypes.c_int
     lib.pdd_last_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.c_int]
     lib.pdd_last_stats.restype = ctypes.c_int
     lib.pdd_last_timing.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
@@ -235,6 +249,27 @@ def autotune_batch(ctx: Context, xyz, offsets, keeps, k: int, sample: int = 0, b
                                           ctypes.byref(out), ctypes.byref(ms)), "pdd_autotune_batch")
     return {"b": int(out.b), "voxel_log2": int(out.voxel_log2), "round_frac": float(out.round_frac),
             "best_ms": float(ms.value)}
+
+
+def quality(ctx: Context, xyz, r2, with_counts: bool = True):
+    """The quality measures of a cloud (pdd_quality_measure): returns
+    (summary dict, counts [m, R] int32 tensor or None, nn2 [m] int64 tensor)."""
+    import numpy as np
+    import torch
+    pts, stride = _points(xyz)
+    m = pts.shape[0]
+    r2a = np.ascontiguousarray(r2, dtype=np.int64)
+    R = len(r2a)
+    counts = torch.empty((m, R), dtype=torch.int32, device=pts.device) if with_counts else None
+    nn2 = torch.empty(m, dtype=torch.int64, device=pts.device)
+    q = Quality()
+    ctx._check(ctx.lib.pdd_quality_measure(ctx.h, _ptr(pts), m, stride, r2a.ctypes.data_as(ctypes.c_void_p), R,
+                                           _ptr(counts), _ptr(nn2), ctypes.byref(q)), "pdd_quality_measure")
+    summ = {"m": int(q.m), "area_m2": list(q.area_m2[:R]), "mean": list(q.mean[:R]),
+            "fractiles": [list(q.fractile[r]) for r in range(R)], "sum": list(q.sum[:R]),
+            "sum_sq": list(q.sum_sq[:R]), "slope": q.slope, "intercept": q.intercept, "r_squared": q.r_squared,
+            "rmse": q.rmse, "nn2_min": int(q.nn2_min), "fractile_capped": bool(q.fractile_capped)}
+    return summ, counts, nn2
 
 
 def decimate_batch(ctx: Context, xyz, offsets, keeps, k: int, b: int = 0, voxel_log2: int = 0,
