@@ -17,10 +17,11 @@ line with
                 matches the workload, list width and kernel source;
   cpu_baseline  the CPU oracle (one core) on a bounded window of the same
                 scan.
-config.plain holds the same steps without the learned search region, and
+config.plain holds the same steps without the learned search region,
 config.batched the batch workload at 1/16 size (256 scans): one autotuned
 pdd_decimate_batch per step against the same scans one pdd_decimate at a
-time, with the kept sets compared.
+time, with the kept sets compared, and config.quality the measures of Sec. 6
+on the kept points (pdd_quality_measure; not timed).
 """
 from __future__ import annotations
 
@@ -81,6 +82,7 @@ def cpu_baseline(w, rows_cols):
 
 GRIDS = {1: (500, 400), 2: (5000, 4000)}
 BATCH_SCALE = 0.0625  # the batch workload beside the single-scan line: 256 scans, 1/16 sizes
+QUALITY_R2 = [v * v for v in (100, 200, 300, 400, 500)]  # squared radii (mm^2) of the kept set's quality measures
 
 
 def batch_compare(ctx, steps, warmup, learned):
@@ -263,6 +265,22 @@ def main():
             "kernel": kname, "algorithmic_bytes_per_launch": algo,
             "bytes_per_point": bytes_per_point, "avg_launch_ms": knn_ms}
 
+    quality = None
+    if not batch:
+        # the measures of Sec. 6 on the kept points of the last step (not
+        # timed): density from the slope of neighbour count against area, R^2,
+        # RMSE, and the smallest nearest-neighbour distance (Eq. 2)
+        kidx = torch.sort(kept.long()).values
+        kp = x[kidx].contiguous()
+        tq = time.perf_counter()
+        qs, _, _ = pdd.quality(ctx, kp, QUALITY_R2, with_counts=False)
+        torch.cuda.synchronize()
+        quality = {"points": int(kp.shape[0]), "radii_mm": [int(round(v ** 0.5)) for v in QUALITY_R2],
+                   "mean_count": [round(v, 3) for v in qs["mean"]], "median_count": [f[3] for f in qs["fractiles"]],
+                   "density_per_m2": round(qs["slope"], 2), "r_squared": round(qs["r_squared"], 4),
+                   "rmse": round(qs["rmse"], 3), "nn_min_mm": round(qs["nn2_min"] ** 0.5, 2),
+                   "ms": round((time.perf_counter() - tq) * 1e3, 1)}
+
     batched = None
     if not args.no_batch and not batch:
         print("batch workload: batched vs one at a time", file=sys.stderr, flush=True)
@@ -290,7 +308,7 @@ def main():
                    "method": "+".join([m for m, on in (("batched", batch), ("autotuned", tune is not None),
                                                         ("learned", pred is not None)) if on]) or "plain",
                    "clouds": int(len(w.keeps)) if batch else 1, "autotune": tune, "predictor": pred,
-                   "plain": plain, "batched": batched,
+                   "plain": plain, "batched": batched, "quality": quality,
                    "gen_s": round(t_gen, 2), "stats": st, "phase_ms": ph},
         "roofline": roof,
         "cpu_baseline": cpu,
