@@ -83,3 +83,25 @@ def test_argument_errors(gpu):
         assert e.value.status == pdd.PDD_EINVAL
     with pytest.raises(pdd.PddError):
         pdd.quality(gpu, x[:1], [100])
+
+
+def test_decimation_is_more_even_than_a_random_subset(gpu):
+    # the claim of Sec. 6 on one scan: the greedy keeps a set whose smallest
+    # nearest-neighbour distance (Eq. 2) is larger, and whose neighbour
+    # counts vary less, than a random subset of the same size
+    import torch
+    from paper_2311_17604_amd import pdd
+    w = scangen.config(1, scale=0.25)
+    x = torch.from_numpy(w.xyz).cuda()
+    kept, _, _ = pdd.decimate(gpu, x, w.keep, w.k)
+    gpu.stream.synchronize()
+    rng = np.random.default_rng(3)
+    rand = np.sort(rng.choice(len(w.xyz), w.keep, replace=False))
+    r2 = [v * v for v in (50, 100, 150, 200)]
+    sd, _, _ = pdd.quality(gpu, torch.from_numpy(w.xyz[np.sort(kept.cpu().numpy())]).cuda(), r2, with_counts=False)
+    sr, _, _ = pdd.quality(gpu, torch.from_numpy(w.xyz[rand]).cuda(), r2, with_counts=False)
+    assert sd["nn2_min"] > sr["nn2_min"]
+    for r in range(len(r2)):
+        band_d = sd["fractiles"][r][5] - sd["fractiles"][r][1]
+        band_r = sr["fractiles"][r][5] - sr["fractiles"][r][1]
+        assert band_d <= band_r, (r, sd["fractiles"][r], sr["fractiles"][r])
