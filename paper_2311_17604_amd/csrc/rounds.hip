@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(1024) rb_refine(RoundArrays a) {
     RoundDev* st = a.st;
     if (st->done || st->err || st->mode != 1) return;
     __shared__ uint32_t h[kSelBins];
-    __shared__ uint32_t s_nc, s_bin, s_need, s_out;
+    __shared__ uint32_t s_bin, s_need, s_out;
     __shared__ uint64_t sc[kSelFinal];
     __shared__ int32_t so[kSelFinal];
     __shared__ uint32_t si[kSelFinal];

@@ -152,3 +152,28 @@ def test_predictor_gain_and_exactness(gpu, oracle_mod, trained):
         if name == "order_cost":
             g_ = g_.view(np.uint64)
         assert np.array_equal(g_, r_), name
+
+
+def test_batch_with_predictor_equals_oracle(gpu, oracle_mod, trained):
+    # the learned region inside a batched decimation (one segmented grid of
+    # 12 scans): each scan's result is still the oracle's
+    import torch
+    from paper_2311_17604_amd import pdd
+    params, _ = trained
+    pdd.pred_set_weights(gpu, params)
+    w = scangen.batch_config(12, scale=1 / 100, base_seed=10500)
+    x = torch.from_numpy(w.xyz).cuda()
+    pdd.pred_enable(gpu, True, 0.25)
+    try:
+        kept, order, oc = pdd.decimate_batch(gpu, x, w.offsets, w.keeps, w.k, b=8)
+        gpu.stream.synchronize()
+    finally:
+        pdd.pred_enable(gpu, False)
+    kept, order, oc = kept.cpu().numpy(), order.cpu().numpy(), oc.cpu().numpy().view(np.uint64)
+    ko = np.concatenate([[0], np.cumsum(w.keeps)])
+    ro = np.concatenate([[0], np.cumsum(np.diff(w.offsets) - w.keeps)])
+    for s in range(len(w.keeps)):
+        ref = oracle_mod.decimate(w.xyz[w.offsets[s]:w.offsets[s + 1]], w.k, int(w.keeps[s]), b=6)
+        assert np.array_equal(kept[ko[s]:ko[s + 1]], ref[0]), ("kept", s)
+        assert np.array_equal(order[ro[s]:ro[s + 1]], ref[1]), ("order", s)
+        assert np.array_equal(oc[ro[s]:ro[s + 1]], ref[2]), ("order_cost", s)
