@@ -72,6 +72,8 @@ typedef struct {
 #define PDD_F_CHECK 1       /* extra device-side invariant checks (slower) */
 #define PDD_F_TIMING 2      /* record HIP events per phase (see pdd_last_timing) */
 #define PDD_F_PROGRESS 4    /* print a progress line to stderr every 50 removal rounds */
+#define PDD_F_EAGER 8       /* launch each round's kernels one by one; by default a single cloud's
+                               round is captured once as a hipGraph and replayed every round */
 
 /* Create a context on HIP device `hip_device` that enqueues its work on
  * `hip_stream` (a hipStream_t; NULL = the null stream).  *out receives the
@@ -233,7 +235,7 @@ int pdd_quality_measure(pdd_ctx *ctx, const int32_t *d_xyz, int64_t m, int32_t s
                         int32_t R, uint32_t *d_counts, int64_t *d_nn2, pdd_quality *out);
 
 /* Counters of the last pdd_decimate on this context, written to stats[0..n),
- * n <= 14:
+ * n <= 15:
  *   0 rounds, 1 re-searches (buffer exhausted), 2 danger checks, 3 reverse-list
  *   rebuilds, 4 device bytes the context's scratch pool holds after the call
  *   (its high-water mark), 5 finest cell level (log2 mm), 6 list width used,
@@ -241,7 +243,8 @@ int pdd_quality_measure(pdd_ctx *ctx, const int32_t *d_xyz, int64_t m, int32_t s
  *   9 lists certified in predicted regions, 10 lists in predicted regions
  *   that were not (searched again by the shell search), 11 points whose
  *   tile could not certify their list (all searched again), 12 points tested
- *   by the re-searches, 13 survivors enumerated by the danger checks.
+ *   by the re-searches, 13 survivors enumerated by the danger checks, 14
+ *   rounds launched as a replay of the captured round graph.
  * Entries 8-10 are also written by pdd_knn_cost.  After pdd_decimate_batch
  * the counters are summed over its groups of clouds (4-6: the last group's).
  * Returns the number of counters written. */

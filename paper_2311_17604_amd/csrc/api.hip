@@ -85,7 +85,11 @@ int pdd_ctx_create(pdd_ctx** out, int hip_device, void* hip_stream) {
     c->stream = (hipStream_t)hip_stream;
     hipError_t e = hipSetDevice(hip_device);
     if (e == hipSuccess) e = hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault);
+    // a stream to capture the round graph on (capture needs a stream other
+    // than the default one; nothing ever runs on it)
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
+        if (c->pinned) (void)hipHostFree(c->pinned);
         delete x;
         return PDD_EHIP;
     }
@@ -103,6 +107,7 @@ void pdd_ctx_destroy(pdd_ctx* ctx) {
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->pred_P) (void)hipFree(c->pred_P);
     if (c->pred_M) (void)hipFree(c->pred_M);
     if (c->pred_V) (void)hipFree(c->pred_V);
@@ -204,6 +209,7 @@ int pdd::decimate_entry(Ctx* c, const int32_t* d_xyz, int64_t n, const int64_t* 
     for (auto& t : c->phase_ms) t = 0.0f;
     c->timing = (opts->flags & PDD_F_TIMING) != 0;
     c->progress = (opts->flags & PDD_F_PROGRESS) != 0;
+    c->eager = (opts->flags & PDD_F_EAGER) != 0;
     if (c->timing && !c->ev[0])
         for (auto& e : c->ev)
             if (hipEventCreate(&e) != hipSuccess) return PDD_EHIP;

@@ -19,7 +19,7 @@ constexpr int kSelBins0 = 4160;     // first-level bins of the threshold select 
 constexpr int kSelBins = 4096;      // refinement bins (12-bit digits)
 constexpr int kSelFinal = 2048;     // candidates resolved by one block sort
 constexpr int kScratchSlots = 128;  // scratch buffers of a context
-constexpr int kNumStats = 14;       // counters reported by pdd_last_stats
+constexpr int kNumStats = 15;       // counters reported by pdd_last_stats
 
 // ---------------------------------------------------------------------------
 // small device helpers
@@ -186,6 +186,8 @@ struct Ctx {
     // phase timing (PDD_F_TIMING): events recorded on the context's stream
     bool timing = false;
     bool progress = false;    // PDD_F_PROGRESS: a line to stderr every 50 rounds
+    bool eager = false;       // PDD_F_EAGER: no hipGraph replay of the rounds
+    hipStream_t cap_stream = nullptr;  // private stream the round graph is captured on (never run)
     unsigned round_blocks = 1024;  // workgroups per launch of the round kernels
     hipEvent_t ev[8] = {};
     float phase_ms[8] = {0};

@@ -1195,6 +1195,44 @@ int launch_round(Ctx* c, RoundArrays& a, const GridView& g, const GridView& gs) 
     return PDD_OK;
 }
 
+// One round's kernels as a hipGraph.  Every kernel of a round reads its
+// sizes and decisions from the device state, so one capture serves every
+// round with the same arguments.  It is taken once the first round has
+// allocated every buffer the round uses, on the context's private capture
+// stream (nothing runs there), and again after a rebuild between rounds; the
+// graph is launched on the context's stream.  Single clouds only: a batch's
+// budget cut sizes a sort on the host.  A failed capture leaves the rounds
+// eager.
+struct RoundGraph {
+    hipGraphExec_t exec = nullptr;
+    ~RoundGraph() { reset(); }
+    void reset() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+    }
+};
+
+template <int K>
+void capture_round(Ctx* c, RoundArrays& a, const GridView& g, const GridView& gs, RoundGraph* rg) {
+    rg->reset();
+    hipStream_t run = c->stream;
+    if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    c->stream = c->cap_stream;
+    const int rc = launch_round<K>(c, a, g, gs);
+    c->stream = run;
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (rc == PDD_OK && e == hipSuccess && graph) {
+        if (hipGraphInstantiate(&rg->exec, graph, nullptr, nullptr, 0) != hipSuccess) rg->exec = nullptr;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    c->err.clear();
+}
+
 template <int K>
 int run_rounds(Ctx* c, RoundArrays& a, const GridView& g, uint32_t n) {
     RoundDev* hst = (RoundDev*)c->pinned;
@@ -1202,9 +1240,16 @@ int run_rounds(Ctx* c, RoundArrays& a, const GridView& g, uint32_t n) {
     int rc = build_alive_view(c, a, g, &gs);
     if (rc) return rc;
     uint32_t view_alive = n;
+    RoundGraph rg;
+    const bool graphs = a.nseg == 1 && !c->eager && c->cap_stream;
     for (uint64_t it = 0;; it++) {
-        rc = launch_round<K>(c, a, g, gs);
-        if (rc) return rc;
+        if (rg.exec) {
+            PDD_HIP(c, hipGraphLaunch(rg.exec, c->stream));
+            c->stats[14]++;
+        } else {
+            rc = launch_round<K>(c, a, g, gs);
+            if (rc) return rc;
+        }
         PDD_HIP(c, hipMemcpyAsync(hst, a.st, sizeof(RoundDev), hipMemcpyDeviceToHost, c->stream));
         PDD_HIP(c, hipStreamSynchronize(c->stream));
         if (hst->err) {
@@ -1232,12 +1277,15 @@ int run_rounds(Ctx* c, RoundArrays& a, const GridView& g, uint32_t n) {
         if (hst->overflow || (uint64_t)hst->pool_count > 12ull * hst->n_alive_new) {
             if ((rc = build_reverse(c, a, n, a.alive_list[hst->apar], hst->n_list))) return rc;
             c->stats[3]++;
+            rg.reset();
         }
         // re-pack the alive search view once a third of its points are gone
         if ((uint64_t)hst->n_alive_new * 3 < (uint64_t)view_alive * 2) {
             if ((rc = build_alive_view(c, a, g, &gs))) return rc;
             view_alive = hst->n_alive_new;
+            rg.reset();
         }
+        if (graphs && !rg.exec) capture_round<K>(c, a, g, gs, &rg);
         if (it > (uint64_t)n + 16) {
             c->err = "round loop made no progress";
             return PDD_EINTERNAL;
@@ -1367,6 +1415,7 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, cons
     if ((rc = build_reverse(c, a, n, a.alive_list[0], n))) return rc;
     mark(c, kPhReverse);
     c->stats[3] = 0;
+    c->stats[14] = 0;
 
     switch (K) {
         case 8: rc = run_rounds<8>(c, a, g, n); break;

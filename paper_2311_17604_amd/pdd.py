@@ -16,11 +16,12 @@ PDD_OK, PDD_EINVAL, PDD_ERANGE, PDD_ENOMEM, PDD_EHIP, PDD_EINTERNAL = range(6)
 PDD_F_CHECK = 1
 PDD_F_TIMING = 2
 PDD_F_PROGRESS = 4
+PDD_F_EAGER = 8
 PHASES = ("grid", "knn", "reverse", "rounds", "final")
 
 STATS = ("rounds", "researches", "danger_checks", "reverse_rebuilds", "scratch_bytes", "voxel_log2",
          "list_width", "touched", "knn_tested", "pred_hits", "pred_misses", "knn_fallbacks",
-         "research_tested", "danger_enumerated")
+         "research_tested", "danger_enumerated", "graph_rounds")
 PRED_NPARAM = 8385
 
 _lib = None
@@ -194,7 +195,7 @@ def grid_info(ctx: Context, xyz, voxel_log2: int = 0):
 
 def decimate(ctx: Context, xyz, keep: int, k: int, b: int = 0, voxel_log2: int = 0, round_frac: float = 0.0,
              check: bool = False, with_order: bool = True, out=None, timing: bool = False,
-             progress: bool = False, round_blocks: int = 0):
+             progress: bool = False, round_blocks: int = 0, eager: bool = False):
     """Greedy decimation to `keep` points.  Returns (kept [keep] int32,
     order [n-keep] int32 or None, order_cost [n-keep] int64 (uint64 bits) or
     None).  `out` may supply preallocated (kept, order, order_cost)."""
@@ -209,7 +210,7 @@ def decimate(ctx: Context, xyz, keep: int, k: int, b: int = 0, voxel_log2: int =
         order_cost = torch.empty(n - keep, dtype=torch.int64, device=pts.device) if with_order else None
     o = Opts(k=k, b=b, voxel_log2=voxel_log2, round_frac=round_frac, point_stride=stride,
              flags=(PDD_F_CHECK if check else 0) | (PDD_F_TIMING if timing else 0)
-             | (PDD_F_PROGRESS if progress else 0), round_blocks=round_blocks)
+             | (PDD_F_PROGRESS if progress else 0) | (PDD_F_EAGER if eager else 0), round_blocks=round_blocks)
     ctx._check(ctx.lib.pdd_decimate(ctx.h, _ptr(pts), n, keep, ctypes.byref(o), _ptr(kept), _ptr(order),
                                     _ptr(order_cost)), "pdd_decimate")
     return kept, order, order_cost

@@ -188,3 +188,22 @@ def test_decimate_range_error(gpu):
     with pytest.raises(pdd.PddError) as e:
         gpu_decimate(gpu, P, 2, 1)
     assert e.value.status == pdd.PDD_ERANGE
+
+
+@pytest.mark.parametrize("scale,frac", [(0.3, 0.01), (0.3, 0.3)])
+def test_round_graph_equals_eager(gpu, oracle_mod, scale, frac):
+    # a single cloud's round is captured once as a hipGraph and replayed
+    # every round (re-captured after the rebuilds between rounds); the same
+    # decimation with every kernel launched eagerly, and the oracle, agree,
+    # on one context with eager work between the graph runs
+    w = scangen.config(1, scale=scale)
+    ref = oracle_mod.decimate(w.xyz, w.k, w.keep, b=6)
+    for eager in (False, True, False):
+        got = gpu_decimate(gpu, w.xyz, w.keep, w.k, round_frac=frac, eager=eager)
+        st = gpu.stats()
+        for g, r, name in zip(got, ref, ("kept", "order", "order_cost")):
+            assert np.array_equal(g, r), (name, eager)
+        if eager:
+            assert st["graph_rounds"] == 0
+        else:
+            assert 0 < st["graph_rounds"] <= st["rounds"], st
