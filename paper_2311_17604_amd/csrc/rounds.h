@@ -48,6 +48,7 @@ struct RoundArrays {
     uint32_t* inA;      // round stamps
     uint32_t* blocked;
     uint32_t* touched;
+    uint32_t* win;      // [n] bit j set: entry j of the list is summed in the cost
     uint32_t* surv;
     uint32_t* alive_list[2];
     int4* apts;              // alive search view (.w = -1 once removed)

@@ -656,36 +656,75 @@ __global__ void __launch_bounds__(kBlock) rb_touch_recost(RoundArrays a) {
         const bool fresh = valid && a.alive[z] && atomicExch(&a.touched[z], round) != round;
         bool rs = false;
         if (fresh) {
+            // z's cost is the exact sum of the terms of the entries that
+            // win[z] marks: the first k of its list that were alive before
+            // this round.  The new cost takes off the terms of the marked
+            // entries removed this round and adds those of the next alive
+            // entries past the marked ones, so only their points are read.
             const int4 pz = a.pts[z];
             const int c = a.cnt[z];
+            const uint32_t win = a.win[z];
+            const int wend = win ? 32 - __builtin_clz(win) : 0;  // positions [0, wend) hold every marked entry
             const int32_t* nb = a.nbr + (size_t)z * K;
-            int nvalid = 0;
-            uint64_t wsum = 0;
+            int nnew = 0;       // alive entries of the new window
+            uint32_t nwin = 0;  // and their positions
+            uint64_t sub = 0, add = 0;
             // eight entries at a time (K is a multiple of 8 and every list
-            // starts 32-byte aligned): their ids in two loads, then all their
-            // alive flags, then the points of the alive ones, so that the
-            // gathers of a chunk are in flight together
-            for (int j0 = 0; j0 < c && nvalid < k; j0 += 8) {
+            // starts 32-byte aligned): their ids in two loads, then their
+            // alive flags, then the points whose terms change, each batch of
+            // gathers in flight together
+            for (int j0 = 0; j0 < c && (j0 < wend || nnew < k); j0 += 8) {
                 const int4 v0 = *(const int4*)(nb + j0), v1 = *(const int4*)(nb + j0 + 4);
-                const int32_t ys[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-                bool al[8];
+                const uint32_t ys[8] = {(uint32_t)v0.x, (uint32_t)v0.y, (uint32_t)v0.z, (uint32_t)v0.w,
+                                        (uint32_t)v1.x, (uint32_t)v1.y, (uint32_t)v1.z, (uint32_t)v1.w};
+                bool al[8], chg[8];
 #pragma unroll
-                for (int i = 0; i < 8; i++) al[i] = j0 + i < c && a.alive[(uint32_t)ys[i]];
+                for (int i = 0; i < 8; i++) al[i] = j0 + i < c && a.alive[ys[i]];
+                // an alive entry outside the window lies past it (every
+                // entry alive now was alive before, and the window holds the
+                // first k of those)
+#pragma unroll
+                for (int i = 0; i < 8; i++) {
+                    const bool marked = (win >> (j0 + i)) & 1u;
+                    chg[i] = marked ? !al[i] : (al[i] && nnew < k);
+                    if (al[i] && (marked || nnew < k)) {
+                        nnew++;
+                        nwin |= 1u << (j0 + i);
+                    }
+                }
                 int4 py[8];
 #pragma unroll
-                for (int i = 0; i < 8; i++) py[i] = al[i] ? a.pts[(uint32_t)ys[i]] : pz;
+                for (int i = 0; i < 8; i++) py[i] = chg[i] ? a.pts[ys[i]] : pz;
 #pragma unroll
                 for (int i = 0; i < 8; i++)
-                    if (al[i] && nvalid < k) {
-                        wsum += cost_term(dist2(pz.x, pz.y, pz.z, py[i].x, py[i].y, py[i].z));
-                        nvalid++;
+                    if (chg[i]) {
+                        const uint64_t t = cost_term(dist2(pz.x, pz.y, pz.z, py[i].x, py[i].y, py[i].z));
+                        if (al[i]) add += t;
+                        else sub += t;
                     }
             }
-            if (nvalid < k && c == K) {
+            if (nnew < k && c == K) {
                 rs = true;
-            } else {
-                if (a.check && wsum > a.cost[z]) st->err = 6;
+            } else if (nwin != win) {
+                const uint64_t old = a.cost[z];
+                const uint64_t wsum = old - sub + add;
+                if (a.check) {
+                    // the full sum over the first k alive entries
+                    uint64_t full = 0;
+                    uint32_t fwin = 0;
+                    int nv = 0;
+                    for (int j = 0; j < c && nv < k; j++) {
+                        const uint32_t y = (uint32_t)nb[j];
+                        if (!a.alive[y]) continue;
+                        const int4 q = a.pts[y];
+                        full += cost_term(dist2(pz.x, pz.y, pz.z, q.x, q.y, q.z));
+                        fwin |= 1u << j;
+                        nv++;
+                    }
+                    if (sub > old || wsum > old || full != wsum || fwin != nwin) st->err = 6;
+                }
                 a.cost[z] = wsum;
+                a.win[z] = nwin;
             }
         }
         ntouched += (uint32_t)__popcll(__ballot(fresh));
@@ -816,6 +855,7 @@ __global__ void __launch_bounds__(kBlock) rb_research(RoundArrays a, GridView g)
             a.cnt[z] = (uint8_t)c;
             if (a.check && wsum > a.cost[z]) st->err = 7;
             a.cost[z] = wsum;
+            a.win[z] = (uint32_t)((1ull << use) - 1ull);
         }
         // reverse edges of the new members, in pool nodes at fixed slots
         // (K per re-search; rb_pool_end advances the pool past them)
@@ -945,6 +985,15 @@ __global__ void __launch_bounds__(kBlock) av_start_k(const uint32_t* __restrict_
         astart[c] = pos[start[c]];
 }
 
+// The cost of a fresh list sums its first min(k, cnt) entries.
+__global__ void __launch_bounds__(kBlock) win_init_k(const uint8_t* __restrict__ cnt, uint32_t n, int k,
+                                                     uint32_t* __restrict__ win) {
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+        const int c = cnt[j] < k ? cnt[j] : k;
+        win[j] = (uint32_t)((1ull << c) - 1ull);
+    }
+}
+
 // Runs of identical coordinates (equal Morton codes, hence adjacent in the
 // sorted order): the first point of a run writes the run to all its points.
 __global__ void __launch_bounds__(kBlock) grp_init_k(const int4* __restrict__ pts, const uint32_t* __restrict__ seg,
@@ -1066,7 +1115,7 @@ inline unsigned gfor(size_t count, unsigned maxg = 4096) {
 enum {
     // 0..5 grid build, 40..47 scan partials, 48..50 radix sort, 52..55 order sort, 56..59 k-NN output
     kSAlive = 10, kSCost, kSNbr, kSCnt, kSInA, kSBlocked, kSTouched, kSAl0, kSAl1, kSA, kSC0, kSC1, kSDgY,
-    kSTouch, kSResearch, kSR, kSEvC, kSEvO, kSHist, kSRevOff, kSRevSrc, kSHead, kSPoolS, kSPoolN, kSSt, kSTmp,
+    kSWin, kSResearch, kSR, kSEvC, kSEvO, kSHist, kSRevOff, kSRevSrc, kSHead, kSPoolS, kSPoolN, kSSt, kSTmp,
     kSFin1, kSFin2, kSSurv,
     kSCellAlive = 60, kSCellA, kSDgC, kSDgO, kSDgD, kSSurvOff, kSSurvList, kSSurvBucket, kSCS, kSGrpLo, kSGrpHi,
     kSGSafe, kSAPts, kSAStart, kSAFlag, kSAPos,
@@ -1332,6 +1381,7 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, cons
     ALLOC(inA, kSInA, (size_t)n * 4);
     ALLOC(blocked, kSBlocked, (size_t)n * 4);
     ALLOC(touched, kSTouched, (size_t)n * 4);
+    ALLOC(win, kSWin, (size_t)n * 4);
     ALLOC(surv, kSSurv, (size_t)n * 4);
     ALLOC(alive_list[0], kSAl0, (size_t)n * 4);
     ALLOC(alive_list[1], kSAl1, (size_t)n * 4);
@@ -1411,6 +1461,8 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, cons
     KnnOut ko{a.nbr, a.cnt, a.cost, nullptr};
     mark(c, kPhGrid);
     if ((rc = knn_all(c, g, k, K, ko, nullptr))) return rc;
+    hipLaunchKernelGGL(win_init_k, dim3(gfor(n)), dim3(kBlock), 0, c->stream, a.cnt, n, k, a.win);
+    PDD_HIP(c, hipGetLastError());
     mark(c, kPhKnn);
     if ((rc = build_reverse(c, a, n, a.alive_list[0], n))) return rc;
     mark(c, kPhReverse);
