@@ -210,8 +210,8 @@ __global__ void __launch_bounds__(kBlock) rb_survive(RoundArrays a, GridView g) 
 }
 
 // Groups the survivors by level-0 cell (offsets from the scan of cS), so
-// that the survivors of any cell of any level are one run of surv_bucket;
-// takes cS back to zero on the way.
+// that the survivors of any cell of any level are one run of surv_rec, each
+// with its point and cost; takes cS back to zero on the way.
 __global__ void __launch_bounds__(kBlock) rb_bucket(RoundArrays a) {
     RoundDev* st = a.st;
     if (st->done || st->err) return;
@@ -219,7 +219,17 @@ __global__ void __launch_bounds__(kBlock) rb_bucket(RoundArrays a) {
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ns; t += gridDim.x * blockDim.x) {
         const uint32_t x = a.surv_list[t];
         const uint32_t c = a.of0[x];
-        a.surv_bucket[a.surv_off[c] + atomicSub(&a.cS[c], 1u) - 1u] = x;
+        const uint32_t pos = a.surv_off[c] + atomicSub(&a.cS[c], 1u) - 1u;
+        if (pos < a.rec_cap) {
+            SurvRec r;
+            r.p = a.pts[x];
+            r.cost = a.cost[x];
+            r.x = x;
+            r.pad = 0;
+            a.surv_rec[pos] = r;
+        } else {
+            st->err = 8;
+        }
     }
     // the highest key of each segment's A survives every condition; find
     // its index
@@ -396,16 +406,20 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
                 }
             }
         }
-        auto consider = [&](uint32_t x) {
-            if (x == y || a.surv[x] != round || a.blocked[x] == round) return;  // (gsafe points are not survivors)
-            const uint64_t cx = a.cost[x];
+        // (gsafe points are not survivors; a survivor another check has
+        // blocked already is passed over once it clears the filters)
+        auto consider = [&](const SurvRec& r) {
+            const uint32_t x = r.x;
+            if (x == y) return;
+            const uint64_t cx = r.cost;
             const int lx = level_of(st, cx);
             if (!((risk >> lx) & 1u) || R2[lx] == 0) return;  // safe level, or waiting on glob_block
-            const int4 px = a.pts[x];
+            const int4 px = r.p;
             const uint64_t dxy = dist2(px.x, px.y, px.z, py.x, py.y, py.z);
             if (dxy < dlast || dxy >= R2[lx]) return;
             const int32_t ox = px.w;
             if (key_above(cx, ox, cy, oy) || key_above(cx, ox, tc, to)) return;
+            if (a.blocked[x] == round) return;
             // witnesses not above x within d(x, y) of y
             int q = 0;
             for (int i = 0; i < K; i++) {
@@ -490,7 +504,8 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
 #pragma unroll
                         for (int step = 32; step > 0; step >>= 1)
                             if (s_excl[w][l + step] <= u) l += step;
-                        consider(a.surv_bucket[s_start[w][l] + (u - s_excl[w][l])]);
+                        const uint32_t ri = s_start[w][l] + (u - s_excl[w][l]);
+                        if (ri < a.rec_cap) consider(a.surv_rec[ri]);
                     }
                 }
                 wave_sync_lds();

@@ -38,6 +38,15 @@ struct RoundDev {
     uint64_t surv_min[kLev];      // lowest survivor cost per key level, this round
 };
 
+// A survivor of the round as the danger checks read it: its point (.w the
+// original index), cost and sorted index, in one 32-byte record.
+struct alignas(16) SurvRec {
+    int4 p;
+    uint64_t cost;
+    uint32_t x;
+    uint32_t pad;
+};
+
 struct RoundArrays {
     const int4* pts;
     const uint32_t* of0;    // [n] level-0 cell of each point
@@ -91,7 +100,8 @@ struct RoundArrays {
     uint32_t* ovf;          // [n] A points of over-budget segments
     uint32_t* cS;           // [ncells0 + 1] survivors per level-0 cell, this round
     uint32_t* surv_off;     // [ncells0 + 1] exclusive scan of cS
-    uint32_t* surv_bucket;  // [n] survivors grouped by level-0 cell, in cell order
+    SurvRec* surv_rec;      // [rec_cap] survivors grouped by level-0 cell, in cell order
+    uint32_t rec_cap;       // at least the largest A of any round
     RoundDev* st;
     int k, K;
     float frac;

@@ -35,6 +35,7 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <cmath>
 #include <type_traits>
 #include <vector>
 
@@ -1415,7 +1416,14 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, cons
         }
     ALLOC(surv_off, kSSurvOff, (size_t)(ncells0 + 1) * 4);
     ALLOC(surv_list, kSSurvList, (size_t)n * 4);
-    ALLOC(surv_bucket, kSSurvBucket, (size_t)n * 4);
+    // a round's A holds at most ceil(frac_max * alive) points (rb_begin),
+    // frac_max = min(4 frac, 1) as rd_init sets it
+    {
+        const float fmax = std::fmin(4.0f * frac, 1.0f);
+        const double cap = std::ceil((double)fmax * (double)n) + 1.0;
+        a.rec_cap = cap >= (double)n ? n : (uint32_t)cap;
+    }
+    ALLOC(surv_rec, kSSurvBucket, (size_t)a.rec_cap * sizeof(SurvRec));
     ALLOC(cS, kSCS, (size_t)(ncells0 + 1) * 4);
     uint32_t *glo, *ghi;
     if (!(glo = (uint32_t*)scratch(c, kSGrpLo, (size_t)n * 4)) || !(ghi = (uint32_t*)scratch(c, kSGrpHi, (size_t)n * 4)))
