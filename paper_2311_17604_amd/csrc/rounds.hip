@@ -654,7 +654,20 @@ __global__ void __launch_bounds__(kBlock) rb_touch_recost(RoundArrays a) {
     // touch z (if valid) and re-cost it when this lane touched it first;
     // every lane of the wave calls it
     auto visit = [&](bool valid, uint32_t z) {
-        const bool fresh = valid && a.alive[z] && atomicExch(&a.touched[z], round) != round;
+        // z's alive flag, touch stamp, point, list length and window in one
+        // batch of gathers (a dead z takes the stamp too; nothing reads it)
+        bool fresh = false;
+        int4 pz = make_int4(0, 0, 0, 0);
+        int c = 0;
+        uint32_t win = 0;
+        if (valid) {
+            const uint8_t az = a.alive[z];
+            const uint32_t was = atomicExch(&a.touched[z], round);
+            pz = a.pts[z];
+            c = a.cnt[z];
+            win = a.win[z];
+            fresh = az && was != round;
+        }
         bool rs = false;
         if (fresh) {
             // z's cost is the exact sum of the terms of the entries that
@@ -662,9 +675,6 @@ __global__ void __launch_bounds__(kBlock) rb_touch_recost(RoundArrays a) {
             // this round.  The new cost takes off the terms of the marked
             // entries removed this round and adds those of the next alive
             // entries past the marked ones, so only their points are read.
-            const int4 pz = a.pts[z];
-            const int c = a.cnt[z];
-            const uint32_t win = a.win[z];
             const int wend = win ? 32 - __builtin_clz(win) : 0;  // positions [0, wend) hold every marked entry
             const int32_t* nb = a.nbr + (size_t)z * K;
             int nnew = 0;       // alive entries of the new window
