@@ -149,7 +149,7 @@ def train_predictor(ctx, k, b):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2, help="workload 1..5 (2: 20M-point scan, k=16, keep 10%%)")
     ap.add_argument("--scale", type=float, default=1.0)
