@@ -340,9 +340,13 @@ __global__ void __launch_bounds__(kBlock) rb_collect0(RoundArrays a) {
     }
 }
 
+// candidates per thread and step of rb_refine's passes
+constexpr int kRefineIPT = 8;
+
 // Exact top sel_need of the candidate bin, in one block: 12-bit digits of
 // the key below the first-level prefix until at most kSelFinal remain, then
 // a bitonic sort.
+
 __global__ void __launch_bounds__(1024) rb_refine(RoundArrays a) {
     RoundDev* st = a.st;
     if (st->done || st->err || st->mode != 1) return;
@@ -366,22 +370,48 @@ __global__ void __launch_bounds__(1024) rb_refine(RoundArrays a) {
         for (int i = threadIdx.x; i < kSelBins; i += blockDim.x) h[i] = 0;
         if (threadIdx.x == 0) s_out = 0;
         __syncthreads();
-        for (uint32_t t = threadIdx.x; t < nc; t += blockDim.x) {
-            const uint32_t i = C[t];
-            atomicAdd(&h[key_digit(a.cost[i], a.pts[i].w, lo, w)], 1u);
+        // kRefineIPT candidates per thread at a time: their indices, then
+        // their keys, each batch of loads in flight together
+        for (uint32_t t0 = threadIdx.x; t0 < nc; t0 += blockDim.x * kRefineIPT) {
+            uint32_t ii[kRefineIPT];
+            uint32_t dd[kRefineIPT];
+#pragma unroll
+            for (int e = 0; e < kRefineIPT; e++) {
+                const uint32_t t = t0 + e * blockDim.x;
+                ii[e] = t < nc ? C[t] : kNone;
+            }
+#pragma unroll
+            for (int e = 0; e < kRefineIPT; e++)
+                dd[e] = ii[e] != kNone ? key_digit(a.cost[ii[e]], a.pts[ii[e]].w, lo, w) : 0u;
+#pragma unroll
+            for (int e = 0; e < kRefineIPT; e++)
+                if (ii[e] != kNone) atomicAdd(&h[dd[e]], 1u);
         }
         __syncthreads();
         find_bin(h, 1 << w, need, &s_bin, &s_need);
         const uint32_t dsel = s_bin;
-        for (uint32_t t = threadIdx.x; t < nc; t += blockDim.x) {
-            const uint32_t i = C[t];
-            const uint32_t d = key_digit(a.cost[i], a.pts[i].w, lo, w);
-            if (d > dsel) {
-                const uint32_t p = atomicAdd(&st->nA, 1u);
-                a.A[p] = i;
-                a.inA[i] = round;
-            } else if (d == dsel) {
-                D[atomicAdd(&s_out, 1u)] = i;
+        for (uint32_t t0 = threadIdx.x; t0 < nc; t0 += blockDim.x * kRefineIPT) {
+            uint32_t ii[kRefineIPT];
+            uint32_t dd[kRefineIPT];
+#pragma unroll
+            for (int e = 0; e < kRefineIPT; e++) {
+                const uint32_t t = t0 + e * blockDim.x;
+                ii[e] = t < nc ? C[t] : kNone;
+            }
+#pragma unroll
+            for (int e = 0; e < kRefineIPT; e++)
+                dd[e] = ii[e] != kNone ? key_digit(a.cost[ii[e]], a.pts[ii[e]].w, lo, w) : 0u;
+#pragma unroll
+            for (int e = 0; e < kRefineIPT; e++) {
+                if (ii[e] == kNone) continue;
+                const uint32_t i = ii[e];
+                if (dd[e] > dsel) {
+                    const uint32_t p = atomicAdd(&st->nA, 1u);
+                    a.A[p] = i;
+                    a.inA[i] = round;
+                } else if (dd[e] == dsel) {
+                    D[atomicAdd(&s_out, 1u)] = i;
+                }
             }
         }
         __syncthreads();

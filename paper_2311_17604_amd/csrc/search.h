@@ -248,10 +248,13 @@ __device__ void wave_knn(const GridView& g, uint32_t q, int4 qp, const SearchCtx
         const int s = lv.s;
         const int cx = ux >> s, cy = uy >> s, cz = uz >> s;
         const int rmax = (L == g.nlev - 1) ? (1 << 22) : 1;
+        // below the top level the 3x3x3 block is scanned in one pass (the
+        // centre cell alone almost never certifies k neighbours)
+        const bool whole = rmax == 1;
         // the previous level's block, already tested
         const bool skip = L > L0;
         const int ps = s - 1, px = ux >> ps, py = uy >> ps, pz = uz >> ps;
-        for (int r = 0; r <= rmax; r++) {
+        for (int r = whole ? 1 : 0; r <= rmax; r++) {
             const int side = 2 * r + 1;
             const int ncube = side * side * side;
             for (int base = 0; base < ncube; base += kWave) {
@@ -263,7 +266,7 @@ __device__ void wave_knn(const GridView& g, uint32_t q, int4 qp, const SearchCtx
                     const int dy = rem / side - r, dx = rem % side - r;
                     const int m = max(abs(dx), max(abs(dy), abs(dz)));
                     const int x = cx + dx, y = cy + dy, z = cz + dz;
-                    if (m == r && x >= 0 && y >= 0 && z >= 0 && x <= lv.cmax[0] && y <= lv.cmax[1] &&
+                    if ((m == r || whole) && x >= 0 && y >= 0 && z >= 0 && x <= lv.cmax[0] && y <= lv.cmax[1] &&
                         z <= lv.cmax[2]) {
                         const uint32_t c = hash_find(lv.hkeys, lv.hvals, lv.hmask, cell_code(lv, qs, x, y, z));
                         if (c != kNone) {
