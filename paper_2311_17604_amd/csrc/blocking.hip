@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(kBlock) rb_survive(RoundArrays a, GridView g) 
             if (a.blocked[x] != round && a.gsafe[x] != round) {
                 sv = true;
                 a.surv[x] = round;
-                atomicAdd(&a.cS[a.of0[x]], 1u);
+                atomicOr(&a.sbits[x >> 6], 1ull << (x & 63u));
             }
         }
         // the block's survivors: one shared-counter atomic per block
@@ -209,17 +209,24 @@ __global__ void __launch_bounds__(kBlock) rb_survive(RoundArrays a, GridView g) 
         atomicMin((unsigned long long*)&st->surv_min[threadIdx.x], s_min[threadIdx.x]);
 }
 
-// Groups the survivors by level-0 cell (offsets from the scan of cS), so
-// that the survivors of any cell of any level are one run of surv_rec, each
-// with its point and cost; takes cS back to zero on the way.
+// Puts every survivor's record (point, cost, index) at its rank among the
+// survivors by sorted index, so that the survivors of any cell of any level
+// (a run of sorted indices) are one run of surv_rec.
+// Survivors per 64-point word of the survivor bits (0 past the last word).
+__global__ void __launch_bounds__(kBlock) rb_wcount(RoundArrays a) {
+    RoundDev* st = a.st;
+    if (st->done || st->err) return;
+    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w <= a.nwords; w += gridDim.x * blockDim.x)
+        a.swcnt[w] = w < a.nwords ? (uint32_t)__popcll(a.sbits[w]) : 0u;
+}
+
 __global__ void __launch_bounds__(kBlock) rb_bucket(RoundArrays a) {
     RoundDev* st = a.st;
     if (st->done || st->err) return;
     const uint32_t ns = st->nSurv;
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ns; t += gridDim.x * blockDim.x) {
         const uint32_t x = a.surv_list[t];
-        const uint32_t c = a.of0[x];
-        const uint32_t pos = a.surv_off[c] + atomicSub(&a.cS[c], 1u) - 1u;
+        const uint32_t pos = surv_rank(a, x);
         if (pos < a.rec_cap) {
             SurvRec r;
             r.p = a.pts[x];
@@ -455,8 +462,8 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
         if (rbox != 0) {
             // survivors within sqrt(rbox) of y, from the cells of the level
             // where the box spans at most 4 cells per axis; the survivors of
-            // a cell are the run of the bucket array between the offsets of
-            // its first level-0 cell and the next cell's
+            // a cell are the records ranked between its first point's rank
+            // and the next cell's
             const int ri = (int)sqrt((double)rbox) + 1;
             int se = 0;
             while (se < 21 && (3 << se) < 2 * ri) se++;
@@ -478,10 +485,8 @@ __global__ void __launch_bounds__(kBlock) rb_danger(RoundArrays a, GridView g) {
                     if (gx * gx + gy * gy + gz * gz < rbox) {
                         const uint32_t c = hash_find(lv.hkeys, lv.hvals, lv.hmask, cell_code(lv, ys, xx, yy, zz));
                         if (c != kNone) {
-                            const uint32_t f0 = lv.first0 ? lv.first0[c] : c;
-                            const uint32_t f1 = lv.first0 ? lv.first0[c + 1] : c + 1;
-                            st0 = a.surv_off[f0];
-                            cnt = a.surv_off[f1] - st0;
+                            st0 = surv_rank(a, lv.start[c]);
+                            cnt = surv_rank(a, lv.start[c + 1]) - st0;
                         }
                     }
                 }
@@ -528,7 +533,8 @@ int launch_k(Ctx* c, const RoundArrays& a, const GridView& g) {
     hipLaunchKernelGGL(rb_survive, dim3(G), dim3(kBlock), 0, c->stream, a, g);
     launch_coarse(c, a, g, 0);
     PDD_HIP(c, hipGetLastError());
-    int rc = exclusive_scan_u32(c, a.cS, a.surv_off, a.ncells0 + 1, nullptr);
+    hipLaunchKernelGGL(rb_wcount, dim3(std::min((a.nwords + kBlock) / kBlock, 1024u)), dim3(kBlock), 0, c->stream, a);
+    int rc = exclusive_scan_u32(c, a.swcnt, a.swpre, a.nwords + 1, nullptr);
     if (rc) return rc;
     hipLaunchKernelGGL(rb_bucket, dim3(G), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_danger<K>, dim3(G), dim3(kBlock), 0, c->stream, a, g);

@@ -109,7 +109,6 @@ struct LevelView {
     const uint64_t* hkeys;    // [hmask + 1] Morton cell codes (kEmptyKey = empty slot)
     const uint32_t* hvals;    // [hmask + 1] cell index
     const uint32_t* parent;   // [ncells] cell one level up (nullptr at the top level)
-    const uint32_t* first0;   // [ncells + 1] first level-0 cell inside each cell (level 0: nullptr)
     const uint64_t* key;      // [ncells] Morton code of each cell (coordinates at this level)
     uint32_t hmask;
     uint32_t ncells;
@@ -157,7 +156,6 @@ struct Level {
     uint64_t* hkeys = nullptr;
     uint32_t* hvals = nullptr;
     uint32_t* parent = nullptr;
-    uint32_t* first0 = nullptr;
     uint64_t hcap = 0;
     uint32_t ncells = 0;
 };

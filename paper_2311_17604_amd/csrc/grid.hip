@@ -149,23 +149,18 @@ __global__ void __launch_bounds__(kBlock) up_flag_k(const uint64_t* __restrict__
 }
 
 __global__ void __launch_bounds__(kBlock) up_write_k(const uint64_t* __restrict__ key, const uint32_t* __restrict__ start,
-                                                     const uint32_t* __restrict__ first0, uint32_t nc, uint32_t n,
-                                                     uint32_t nc0, const uint32_t* __restrict__ flag,
+                                                     uint32_t nc, uint32_t n, const uint32_t* __restrict__ flag,
                                                      const uint32_t* __restrict__ pos, uint32_t* __restrict__ parent,
                                                      uint32_t* __restrict__ ustart, uint64_t* __restrict__ ukey,
-                                                     uint32_t* __restrict__ ufirst0, uint32_t unc) {
+                                                     uint32_t unc) {
     for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (size_t)gridDim.x * blockDim.x) {
         parent[c] = pos[c] + flag[c] - 1u;
         if (flag[c]) {
             const uint32_t u = pos[c];
             ustart[u] = start[c];
             ukey[u] = key[c] >> 3;
-            ufirst0[u] = first0 ? first0[c] : (uint32_t)c;
         }
-        if (c == 0) {
-            ustart[unc] = n;
-            ufirst0[unc] = nc0;
-        }
+        if (c == 0) ustart[unc] = n;
     }
 }
 
@@ -239,7 +234,6 @@ static void free_level(Level* l) {
     if (l->hkeys) (void)hipFree(l->hkeys);
     if (l->hvals) (void)hipFree(l->hvals);
     if (l->parent) (void)hipFree(l->parent);
-    if (l->first0) (void)hipFree(l->first0);
     *l = Level();
 }
 
@@ -423,7 +417,6 @@ int build_grid_seg(Ctx* c, const int32_t* xyz, int64_t n64, int stride, int voxe
         lv.start = L->start;
         lv.hkeys = L->hkeys;
         lv.hvals = L->hvals;
-        lv.first0 = L->first0;
         lv.key = L->key;
         lv.hmask = (uint32_t)(L->hcap - 1);
         lv.ncells = L->ncells;
@@ -440,9 +433,8 @@ int build_grid_seg(Ctx* c, const int32_t* xyz, int64_t n64, int stride, int voxe
         if ((rc = alloc_dev(c, (void**)&L->parent, (size_t)nc * 4))) return rc;
         if ((rc = alloc_dev(c, (void**)&U->start, (size_t)(U->ncells + 1) * 4))) return rc;
         if ((rc = alloc_dev(c, (void**)&U->key, (size_t)U->ncells * 8))) return rc;
-        if ((rc = alloc_dev(c, (void**)&U->first0, (size_t)(U->ncells + 1) * 4))) return rc;
-        hipLaunchKernelGGL(up_write_k, dim3(grid_for(nc)), dim3(kBlock), 0, c->stream, L->key, L->start, L->first0, nc,
-                           n, l0->ncells, flag, pos, L->parent, U->start, U->key, U->first0, U->ncells);
+        hipLaunchKernelGGL(up_write_k, dim3(grid_for(nc)), dim3(kBlock), 0, c->stream, L->key, L->start, nc, n, flag,
+                           pos, L->parent, U->start, U->key, U->ncells);
         PDD_HIP(c, hipGetLastError());
         if ((rc = build_hash(c, U))) return rc;
         lv.parent = L->parent;

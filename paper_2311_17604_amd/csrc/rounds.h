@@ -98,15 +98,19 @@ struct RoundArrays {
     uint64_t* seg_top_cost; // [nseg] highest key of the segment's A (never waits), this round
     int32_t* seg_top_orig;  // [nseg]
     uint32_t* ovf;          // [n] A points of over-budget segments
-    uint32_t* cS;           // [ncells0 + 1] survivors per level-0 cell, this round
-    uint32_t* surv_off;     // [ncells0 + 1] exclusive scan of cS
+    // survivors of this round by sorted index: one bit per point, the
+    // survivors in each 64-point word and their exclusive scan; a survivor's
+    // rank among them places its record (cleared by rb_remove)
+    unsigned long long* sbits;  // [nwords]
+    uint32_t* swcnt;            // [nwords + 1]
+    uint32_t* swpre;            // [nwords + 1]
+    uint32_t nwords;
     SurvRec* surv_rec;      // [rec_cap] survivors grouped by level-0 cell, in cell order
     uint32_t rec_cap;       // at least the largest A of any round
     RoundDev* st;
     int k, K;
     float frac;
     int check;
-    uint32_t ncells0;
     int nseg;
 };
 
@@ -208,6 +212,14 @@ __device__ inline int level_of(const RoundDev* st, uint64_t cost) {
 #pragma unroll
     for (int j = 1; j < kLev; j++) l += b >= st->lev_t[j];
     return l;
+}
+
+// Survivors of this round with sorted index below p (p <= n).
+__device__ inline uint32_t surv_rank(const RoundArrays& a, uint32_t p) {
+    const uint32_t w = p >> 6, b = p & 63u;
+    uint32_t r = a.swpre[w];
+    if (b) r += (uint32_t)__popcll(a.sbits[w] & ((1ull << b) - 1ull));
+    return r;
 }
 
 // Per-cell counts of the levels >= a.lc from the level below, level by

@@ -579,6 +579,9 @@ __global__ void __launch_bounds__(kBlock) rb_remove(RoundArrays a, GridView g) {
         bool rm = false;
         if (t < nA) {
             x = a.A[t];
+            // the survivor bits of this round are read no more (every
+            // survivor is in A)
+            a.sbits[x >> 6] = 0ull;
             // an identical point ranked below is a witness for everything:
             // with k of them x is removed whatever its neighbours do
             rm = a.gsafe[x] == round;
@@ -1161,7 +1164,7 @@ enum {
     kSCellAlive = 60, kSCellA, kSDgC, kSDgO, kSDgD, kSSurvOff, kSSurvList, kSSurvBucket, kSCS, kSGrpLo, kSGrpHi,
     kSGSafe, kSAPts, kSAStart, kSAFlag, kSAPos,
     kSOvfK0 = 89, kSOvfV0, kSOvfK1, kSOvfV1, kSSegFirst, kSSeg, kSOff, kSSegCnt, kSSegGlob, kSSegTopC, kSSegTopO,
-    kSPool0 = 101, kSPool1, kSClo
+    kSPool0 = 101, kSPool1, kSClo, kSSwCnt = 105
 };
 // levels with at most this many cells are counted by rb_coarse
 constexpr uint32_t kCoarseCells = 4096;
@@ -1403,7 +1406,7 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, cons
     RoundArrays a{};
     a.pts = g.pts;
     a.of0 = g.of0;
-    const uint32_t ncells0 = g.lv[0].ncells, tcells = g.total_cells;
+    const uint32_t tcells = g.total_cells;
     a.k = k;
     a.K = K;
     a.frac = frac;
@@ -1454,7 +1457,10 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, cons
             a.lc = L;
             break;
         }
-    ALLOC(surv_off, kSSurvOff, (size_t)(ncells0 + 1) * 4);
+    a.nwords = (n + 63) / 64;
+    ALLOC(sbits, kSCS, (size_t)a.nwords * 8);
+    ALLOC(swcnt, kSSwCnt, (size_t)(a.nwords + 1) * 4);
+    ALLOC(swpre, kSSurvOff, (size_t)(a.nwords + 1) * 4);
     ALLOC(surv_list, kSSurvList, (size_t)n * 4);
     // a round's A holds at most ceil(frac_max * alive) points (rb_begin),
     // frac_max = min(4 frac, 1) as rd_init sets it
@@ -1464,14 +1470,12 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, cons
         a.rec_cap = cap >= (double)n ? n : (uint32_t)cap;
     }
     ALLOC(surv_rec, kSSurvBucket, (size_t)a.rec_cap * sizeof(SurvRec));
-    ALLOC(cS, kSCS, (size_t)(ncells0 + 1) * 4);
     uint32_t *glo, *ghi;
     if (!(glo = (uint32_t*)scratch(c, kSGrpLo, (size_t)n * 4)) || !(ghi = (uint32_t*)scratch(c, kSGrpHi, (size_t)n * 4)))
         return PDD_ENOMEM;
     a.grp_lo = glo;
     a.grp_hi = ghi;
     ALLOC(gsafe, kSGSafe, (size_t)n * 4);
-    a.ncells0 = ncells0;
     a.nseg = nseg;
     a.seg = g.seg;
     ALLOC(seg_left, kSSeg, (size_t)nseg * 4);
@@ -1489,7 +1493,7 @@ int decimate(Ctx* c, const Grid& grid, int k, int K, float frac, int check, cons
     if ((rc = fill_u32(c, a.touched, 0, n))) return rc;
     if ((rc = fill_u32(c, a.surv, 0, n))) return rc;
     if ((rc = fill_u32(c, a.cellAlev, 0, (size_t)tcells * kLev))) return rc;
-    if ((rc = fill_u32(c, a.cS, 0, ncells0 + 1))) return rc;
+    if ((rc = fill_u32(c, (uint32_t*)a.sbits, 0, (size_t)a.nwords * 2))) return rc;
     if ((rc = fill_u32(c, a.gsafe, 0, n))) return rc;
     PDD_HIP(c, hipMemcpyAsync(a.seg_left, left.data(), (size_t)nseg * 4, hipMemcpyHostToDevice, c->stream));
     int64_t* doff = (int64_t*)scratch(c, kSOff, (size_t)(nseg + 1) * 8);
