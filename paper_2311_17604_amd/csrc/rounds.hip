@@ -183,39 +183,54 @@ __global__ void rb_pool_check(RoundArrays a) {
 }
 
 // Bin holding the `need`-th largest key (bins counted from the top) and how
-// many of that bin are still needed.  Any block size.
+// many of that bin are still needed (bin 0 and none when the bins hold fewer
+// than `need`; the top bin and none when `need` is 0).  Block sizes that are
+// multiples of the wavefront, up to 1024: each thread sums a run of bins, a
+// block scan of the sums finds the one thread whose run holds the
+// need-th key, and that thread walks its run.
 __device__ void find_bin(const uint32_t* hist, int nbins, uint32_t need, uint32_t* bin_out, uint32_t* need_out) {
-    __shared__ uint32_t part[1024];
-    const int nt = blockDim.x;
+    __shared__ uint32_t wsum[1024 / kWave];
+    __shared__ int found;
+    const int nt = blockDim.x, t = threadIdx.x;
+    const int lane = t & (kWave - 1), wid = t / kWave;
     const int per = (nbins + nt - 1) / nt;
-    const int t = threadIdx.x;
     uint32_t s = 0;
     for (int r = t * per; r < (t + 1) * per && r < nbins; r++) s += hist[nbins - 1 - r];
-    part[t] = s;
+    uint32_t x = s;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) wsum[wid] = x;
+    if (t == 0) found = 0;
     __syncthreads();
-    if (t == 0) {
-        uint32_t cum = 0;
-        bool done = false;
-        for (int u = 0; u < nt && !done; u++) {
-            if (cum + part[u] >= need) {
-                for (int r = u * per; r < (u + 1) * per && r < nbins; r++) {
-                    const uint32_t h = hist[nbins - 1 - r];
-                    if (cum + h >= need) {
-                        *bin_out = (uint32_t)(nbins - 1 - r);
-                        *need_out = need - cum;
-                        done = true;
-                        break;
-                    }
-                    cum += h;
-                }
-            } else {
-                cum += part[u];
-            }
-        }
-        if (!done) {
-            *bin_out = 0;
+    uint32_t base = 0;
+    for (int w = 0; w < wid; w++) base += wsum[w];
+    const uint32_t incl = base + x, excl = incl - s;
+    if (need == 0) {
+        if (t == 0) {
+            *bin_out = (uint32_t)(nbins - 1);
             *need_out = 0;
+            found = 1;
         }
+    } else if (excl < need && incl >= need) {
+        uint32_t cum = excl;
+        for (int r = t * per; r < (t + 1) * per && r < nbins; r++) {
+            const uint32_t h = hist[nbins - 1 - r];
+            if (cum + h >= need) {
+                *bin_out = (uint32_t)(nbins - 1 - r);
+                *need_out = need - cum;
+                break;
+            }
+            cum += h;
+        }
+        found = 1;
+    }
+    __syncthreads();
+    if (t == 0 && !found) {
+        *bin_out = 0;
+        *need_out = 0;
     }
     __syncthreads();
 }
