@@ -1,12 +1,14 @@
 // Which points of A are removed this round (the conditions are stated at the
-// top of rounds.hip).  All kernels here give one wavefront to one point.
+// top of rounds.hip).  The kernels here give one wavefront (rb_pair: half
+// a wavefront) to one point.
 #include "rounds.h"
 
 namespace pdd {
 
 namespace {
 
-// y in A: its list entries, one per lane (lane j < K holds entry j).
+// y in A: its list entries, one per lane of a half wavefront (two points of
+// A per wavefront; lane j < K of a half holds entry j).
 //  - blocks y when an entry of H(y) is nearer than rho'(y);
 //  - blocks every lower A entry x with fewer than k alive entries not in
 //    H(x) (other than x) within d(x, y) of y, or whose distance the list
@@ -15,25 +17,43 @@ namespace {
 //    its list is full and holds fewer than k entries outside A.
 template <int K>
 __global__ void __launch_bounds__(kBlock) rb_pair(RoundArrays a) {
+    static_assert(K <= kWave / 2, "a list fits half a wavefront");
     RoundDev* st = a.st;
     if (st->done || st->err) return;
+    constexpr int W = kBlock / kWave, H = kWave / 2;
+    __shared__ int s_cls[W][kWave];
+    __shared__ uint64_t s_d[W][kWave], s_c[W][kWave];
+    __shared__ int32_t s_o[W][kWave];
     const uint32_t nA = st->nA, round = st->round;
     const int k = a.k;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const uint32_t nw = gridDim.x * (kBlock / kWave);
-    uint32_t ndanger = 0;  // danger entries of this wave (wave-uniform)
-    for (uint32_t t = blockIdx.x * (kBlock / kWave) + w; t < nA; t += nw) {
-        const uint32_t y = a.A[t];
-        const int4 py = a.pts[y];
-        const uint64_t cy = a.cost[y];
+    const int half = lane / H, sub = lane % H, hb = half * H;
+    const uint64_t hmask = 0xFFFFFFFFull << hb;
+    // the half's bits of a ballot, as entry bits
+    auto hballot = [&](bool p) { return (uint32_t)((__ballot(p) & hmask) >> hb); };
+    const uint32_t below_sub = (1u << sub) - 1u;
+    const uint32_t nw = gridDim.x * W;
+    uint32_t ndanger = 0;  // danger entries of this half (kept by its first lane)
+    for (uint32_t t0 = (blockIdx.x * W + w) * 2; t0 < nA; t0 += nw * 2) {
+        const uint32_t t = t0 + (uint32_t)half;
+        const bool act = t < nA;
+        uint32_t y = 0;
+        int4 py = make_int4(0, 0, 0, 0);
+        uint64_t cy = 0;
+        int c = 0;
+        if (act) {
+            y = a.A[t];
+            py = a.pts[y];
+            cy = a.cost[y];
+            c = a.cnt[y];
+        }
         const int32_t oy = py.w;
-        const int c = a.cnt[y];
         int cls = 0;
         uint64_t d = ~0ull, draw = 0, cj = 0;
         int32_t oj = 0;
         uint32_t z = 0;
-        if (lane < c) {
-            z = (uint32_t)a.nbr[(size_t)y * K + lane];
+        if (sub < c) {
+            z = (uint32_t)a.nbr[(size_t)y * K + sub];
             const int4 pz = a.pts[z];
             draw = dist2(py.x, py.y, py.z, pz.x, pz.y, pz.z);
             if (a.alive[z]) {
@@ -47,62 +67,67 @@ __global__ void __launch_bounds__(kBlock) rb_pair(RoundArrays a) {
                 }
             }
         }
-        const uint64_t dlast = c > 0 ? readlane64(draw, c - 1) : 0ull;
+        // cross-lane reads are made by every lane, outside the branches
+        const uint64_t dl = shfl64(draw, hb + (c > 0 ? c - 1 : 0));
+        const uint64_t dlast = c > 0 ? dl : 0ull;
         const bool complete = c < K;
         const bool higher = cls == 2 && key_above(cj, oj, cy, oy);
         const bool low = cls != 0 && !higher;
-        const uint64_t lowm = __ballot(low), highm = __ballot(higher);
-        const uint64_t below_lane = (1ull << lane) - 1ull;
+        const uint32_t lowm = hballot(low), highm = hballot(higher);
+        const uint32_t km = hballot(low && __popc(lowm & below_sub) == k - 1);
+        const uint64_t rho = shfl64(d, hb + (km ? __ffs(km) - 1 : 0));
+        const uint64_t dhigh = shfl64(d, hb + (highm ? __ffs(highm) - 1 : 0));
         // y itself
         bool blocked_self;
-        if (__popcll(lowm) >= k) {
-            const uint64_t km = __ballot(low && __popcll(lowm & below_lane) == k - 1);
-            const uint64_t rho = readlane64(d, __ffsll((unsigned long long)km) - 1);
-            blocked_self = highm && readlane64(d, __ffsll((unsigned long long)highm) - 1) < rho;
-        } else {
-            blocked_self = complete ? highm != 0 : true;
-        }
-        if (lane == 0 && blocked_self) a.blocked[y] = round;
-        // rank counts over the other entries (uniform loop, entries broadcast)
+        if (__popc(lowm) >= k) blocked_self = highm && dhigh < rho;
+        else blocked_self = complete ? highm != 0 : true;
+        if (act && sub == 0 && blocked_self) a.blocked[y] = round;
+        // rank counts over the other entries of the half (entries from LDS)
+        s_cls[w][lane] = cls;
+        s_d[w][lane] = d;
+        s_c[w][lane] = cj;
+        s_o[w][lane] = oj;
+        wave_sync_lds();
         int q = 0, rankA = 0;
         for (int i = 0; i < K; i++) {
-            const int ci = __builtin_amdgcn_readlane(cls, i);
+            const int ci = s_cls[w][hb + i];
             if (ci == 0) continue;
-            const uint64_t di = readlane64(d, i);
-            const uint64_t ki = readlane64(cj, i);
-            const int32_t oi = __builtin_amdgcn_readlane(oj, i);
-            if (i != lane && di <= d && (ci == 1 || key_above(cj, oj, ki, oi))) q++;
-            if (ci == 2 && i != lane && key_above(cj, oj, ki, oi)) rankA++;
+            const uint64_t di = s_d[w][hb + i];
+            const uint64_t ki = s_c[w][hb + i];
+            const int32_t oi = s_o[w][hb + i];
+            if (i != sub && di <= d && (ci == 1 || key_above(cj, oj, ki, oi))) q++;
+            if (ci == 2 && i != sub && key_above(cj, oj, ki, oi)) rankA++;
         }
         const bool lower = cls == 2 && !higher;
         const bool covered = complete || d < dlast;
         if (lower && (q < k || !covered)) a.blocked[z] = round;
         // lower points beyond the list
-        const int nL = __popcll(__ballot(cls == 1)), nAe = __popcll(__ballot(cls == 2));
-        const bool danger = !complete && nL < k;
-        if (lane == 0 && !danger) a.dg_y[t] = kNone;
-        if (danger) {
-            ndanger++;
-            const int need = k - nL;
-            uint64_t tc = cy;
-            int32_t to = oy;
-            if (nAe >= need) {
-                // the need-th lowest key among the alive A entries
-                const uint64_t m = __ballot(cls == 2 && rankA == need - 1);
-                const int l = __ffsll((unsigned long long)m) - 1;
-                tc = readlane64(cj, l);
-                to = __builtin_amdgcn_readlane(oj, l);
-            }
-            // the danger entry sits at y's position in A (no shared counter)
-            if (lane == 0) {
+        const int nL = __popc(hballot(cls == 1)), nAe = __popc(hballot(cls == 2));
+        const int need = k - nL;
+        const uint32_t mm = hballot(cls == 2 && rankA == need - 1);
+        const int ml = hb + (mm ? __ffs(mm) - 1 : 0);
+        const uint64_t tcm = shfl64(cj, ml);
+        const int32_t tom = __shfl(oj, ml, kWave);
+        const bool danger = act && !complete && nL < k;
+        if (act && sub == 0) {
+            if (!danger) {
+                a.dg_y[t] = kNone;
+            } else {
+                ndanger++;
+                // the need-th lowest key among the alive A entries, else y's
+                const bool from_list = nAe >= need;
+                // the danger entry sits at y's position in A (no shared counter)
                 a.dg_y[t] = y;
-                a.dg_tc[t] = tc;
-                a.dg_to[t] = to;
+                a.dg_tc[t] = from_list ? tcm : cy;
+                a.dg_to[t] = from_list ? tom : oy;
                 a.dg_dlast[t] = dlast;
             }
         }
+        wave_sync_lds();
     }
-    if (lane == 0 && ndanger) atomicAdd(&st->nDanger, ndanger);
+    const uint32_t nd = (uint32_t)__builtin_amdgcn_readlane((int)ndanger, 0) +
+                        (uint32_t)__builtin_amdgcn_readlane((int)ndanger, H);
+    if (lane == 0 && nd) atomicAdd(&st->nDanger, nd);
 }
 
 // x in A with at least k alive points of identical coordinates ranked below
