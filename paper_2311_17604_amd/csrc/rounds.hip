@@ -1387,8 +1387,8 @@ int run_rounds(Ctx* c, RoundArrays& a, const GridView& g, uint32_t n) {
             c->stats[3]++;
             rg.reset();
         }
-        // re-pack the alive search view once a third of its points are gone
-        if ((uint64_t)hst->n_alive_new * 3 < (uint64_t)view_alive * 2) {
+        // re-pack the alive search view once a fifth of its points are gone
+        if ((uint64_t)hst->n_alive_new * 5 < (uint64_t)view_alive * 4) {
             if ((rc = build_alive_view(c, a, g, &gs))) return rc;
             view_alive = hst->n_alive_new;
             rg.reset();
