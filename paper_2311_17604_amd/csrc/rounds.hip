@@ -1381,8 +1381,8 @@ int run_rounds(Ctx* c, RoundArrays& a, const GridView& g, uint32_t n) {
             fflush(stderr);
         }
         // rebuild the reverse lists when the appended chains overflowed or
-        // grew longer than twelve nodes per alive point on average
-        if (hst->overflow || (uint64_t)hst->pool_count > 12ull * hst->n_alive_new) {
+        // grew longer than twenty nodes per alive point on average
+        if (hst->overflow || (uint64_t)hst->pool_count > 20ull * hst->n_alive_new) {
             if ((rc = build_reverse(c, a, n, a.alive_list[hst->apar], hst->n_list))) return rc;
             c->stats[3]++;
             rg.reset();
