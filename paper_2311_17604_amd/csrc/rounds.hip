@@ -59,7 +59,7 @@ __device__ inline uint32_t key_digit(uint64_t c, int32_t orig, int lo, int w) {
 // ---------------------------------------------------------------------------
 
 // candidate pool size: kPoolFactor * m points (at least kPoolMin) when built
-constexpr uint32_t kPoolFactor = 8, kPoolMin = 1u << 16;
+constexpr uint32_t kPoolFactor = 16, kPoolMin = 1u << 16;
 
 __global__ void rb_begin(RoundArrays a) {
     RoundDev* st = a.st;
