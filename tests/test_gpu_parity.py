@@ -117,6 +117,19 @@ def test_decimate_random(gpu, oracle_mod, n, box, k, b, keep, frac, voxel, seed)
     assert np.array_equal(got[2], ref[2]), "order_cost"
 
 
+@pytest.mark.parametrize("n", [63, 64, 65, 128, 4096, 4097])
+@pytest.mark.parametrize("box,frac", [(20, 0.3), (200, 0.01)])
+def test_decimate_word_boundaries(gpu, oracle_mod, n, box, frac):
+    # the survivors of a round are ranked through one bit per point in 64-bit
+    # words: clouds that end on, just before and just after a word boundary
+    P = scangen.random_cloud(n, box, n + box)
+    keep = max(1, n // 4)
+    ref = oracle_mod.decimate(P, 8, keep, b=2)
+    got = gpu_decimate(gpu, P, keep, 8, round_frac=frac, check=True)
+    for g, r, name in zip(got, ref, ("kept", "order", "order_cost")):
+        assert np.array_equal(g, r), name
+
+
 @pytest.mark.parametrize("scale,frac", [(0.1, 0.03), (1.0, 0.03), (1.0, 0.1)])
 def test_decimate_scan(gpu, oracle_mod, scale, frac):
     w = scangen.config(1, scale=scale)
