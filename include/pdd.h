@@ -72,8 +72,9 @@ typedef struct {
 #define PDD_F_CHECK 1       /* extra device-side invariant checks (slower) */
 #define PDD_F_TIMING 2      /* record HIP events per phase (see pdd_last_timing) */
 #define PDD_F_PROGRESS 4    /* print a progress line to stderr every 50 removal rounds */
-#define PDD_F_EAGER 8       /* launch each round's kernels one by one; by default a single cloud's
-                               round is captured once as a hipGraph and replayed every round */
+#define PDD_F_EAGER 8       /* launch each round's kernels one by one; by default a round is
+                               captured as a hipGraph (a batch's as two, around the host-sized
+                               budget cut) and replayed every round */
 
 /* Create a context on HIP device `hip_device` that enqueues its work on
  * `hip_stream` (a hipStream_t; NULL = the null stream).  *out receives the

@@ -559,7 +559,9 @@ int launch_k(Ctx* c, const RoundArrays& a, const GridView& g) {
     launch_coarse(c, a, g, 0);
     PDD_HIP(c, hipGetLastError());
     hipLaunchKernelGGL(rb_wcount, dim3(std::min((a.nwords + kBlock) / kBlock, 1024u)), dim3(kBlock), 0, c->stream, a);
-    int rc = exclusive_scan_u32(c, a.swcnt, a.swpre, a.nwords + 1, nullptr);
+    // slots of its own: a captured round keeps their addresses while the
+    // budget cut of a batch sorts between its two graphs
+    int rc = exclusive_scan_u32_at(c, a.swcnt, a.swpre, a.nwords + 1, nullptr, kSlotSurvScan, 4);
     if (rc) return rc;
     hipLaunchKernelGGL(rb_bucket, dim3(G), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_danger<K>, dim3(G), dim3(kBlock), 0, c->stream, a, g);

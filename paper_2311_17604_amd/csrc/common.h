@@ -217,6 +217,9 @@ int hip_fail(Ctx* c, hipError_t e, const char* what);
 
 // scan / sort (scan_sort.hip)
 int exclusive_scan_u32(Ctx* c, const uint32_t* in, uint32_t* out, uint32_t count, uint32_t* total_dev);
+// the same with its partial sums in scratch slots slot0 .. slot0 + levels - 1
+int exclusive_scan_u32_at(Ctx* c, const uint32_t* in, uint32_t* out, uint32_t count, uint32_t* total_dev,
+                          int slot0, int levels);
 int exclusive_scan_u32_u64(Ctx* c, const uint32_t* in, uint64_t* out, uint32_t count);
 int radix_sort_pairs(Ctx* c, uint64_t* keys, uint32_t* vals, uint32_t n, int bits, uint64_t** keys_out,
                      uint32_t** vals_out);

@@ -47,6 +47,9 @@ struct alignas(16) SurvRec {
     uint32_t pad;
 };
 
+// scratch slots of the survivor-word scan inside a round (116 .. 119)
+constexpr int kSlotSurvScan = 116;
+
 struct RoundArrays {
     const int4* pts;
     const uint32_t* of0;    // [n] level-0 cell of each point

@@ -1237,10 +1237,10 @@ int build_alive_view(Ctx* c, RoundArrays& a, const GridView& g, GridView* gs) {
 // A batch: keep, in each segment whose A exceeds its remaining budget B_s,
 // only its top B_s keys (A stays an upper set of every segment's keys).
 // Reads the count of such A points back to size the sort.
+// A batch's budget cut after the A counts per segment (rb_seg_count,
+// rb_seg_over): reads back how many A points lie in segments over budget
+// and sorts them, by a sort that this count sizes.
 int segment_budgets(Ctx* c, RoundArrays& a) {
-    hipLaunchKernelGGL(rb_seg_count, dim3(1024), dim3(kBlock), 0, c->stream, a);
-    hipLaunchKernelGGL(rb_seg_over, dim3(1024), dim3(kBlock), 0, c->stream, a);
-    PDD_HIP(c, hipGetLastError());
     uint32_t* h = (uint32_t*)((char*)c->pinned + 2048);
     PDD_HIP(c, hipMemcpyAsync(h, &a.st->nOvf, 4, hipMemcpyDeviceToHost, c->stream));
     PDD_HIP(c, hipStreamSynchronize(c->stream));
@@ -1275,11 +1275,11 @@ int segment_budgets(Ctx* c, RoundArrays& a) {
     return PDD_OK;
 }
 
-template <int K>
-int launch_round(Ctx* c, RoundArrays& a, const GridView& g, const GridView& gs) {
-    // per-item kernels take the configured launch size; the passes over
-    // the alive points or the pool a fixed one
-    const unsigned G = c->round_blocks, GS = 1024;
+// A round in two parts, with a batch's budget cut (sized on the host)
+// between them: the selection of A, then the round rule, the removals and
+// the re-costing.
+void launch_round_a(Ctx* c, RoundArrays& a) {
+    const unsigned GS = 1024;  // passes over the alive points or the pool
     hipLaunchKernelGGL(rb_begin, dim3(1), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_seg_reset, dim3(gfor(a.nseg)), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_hist0, dim3(GS), dim3(kBlock), 0, c->stream, a, 0);
@@ -1288,10 +1288,17 @@ int launch_round(Ctx* c, RoundArrays& a, const GridView& g, const GridView& gs) 
     hipLaunchKernelGGL(rb_find0, dim3(1), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_collect0, dim3(GS), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(rb_refine, dim3(1), dim3(1024), 0, c->stream, a);
-    PDD_HIP(c, hipGetLastError());
-    int rc;
-    if (a.nseg > 1 && (rc = segment_budgets(c, a))) return rc;
-    rc = launch_blocking(c, a, g, K);
+    if (a.nseg > 1) {
+        hipLaunchKernelGGL(rb_seg_count, dim3(1024), dim3(kBlock), 0, c->stream, a);
+        hipLaunchKernelGGL(rb_seg_over, dim3(1024), dim3(kBlock), 0, c->stream, a);
+    }
+}
+
+template <int K>
+int launch_round_b(Ctx* c, RoundArrays& a, const GridView& g, const GridView& gs) {
+    // per-item kernels take the configured launch size
+    const unsigned G = c->round_blocks;
+    int rc = launch_blocking(c, a, g, K);
     if (rc) return rc;
     hipLaunchKernelGGL(rb_remove, dim3(G), dim3(kBlock), 0, c->stream, a, g);
     hipLaunchKernelGGL(rb_remove_end, dim3(1), dim3(1), 0, c->stream, a);
@@ -1303,14 +1310,25 @@ int launch_round(Ctx* c, RoundArrays& a, const GridView& g, const GridView& gs) 
     return PDD_OK;
 }
 
-// One round's kernels as a hipGraph.  Every kernel of a round reads its
-// sizes and decisions from the device state, so one capture serves every
-// round with the same arguments.  It is taken once the first round has
-// allocated every buffer the round uses, on the context's private capture
-// stream (nothing runs there), and again after a rebuild between rounds; the
-// graph is launched on the context's stream.  Single clouds only: a batch's
-// budget cut sizes a sort on the host.  A failed capture leaves the rounds
-// eager.
+template <int K>
+int launch_round(Ctx* c, RoundArrays& a, const GridView& g, const GridView& gs) {
+    launch_round_a(c, a);
+    PDD_HIP(c, hipGetLastError());
+    int rc;
+    if (a.nseg > 1 && (rc = segment_budgets(c, a))) return rc;
+    return launch_round_b<K>(c, a, g, gs);
+}
+
+// A round's kernels as hipGraphs.  Every kernel of a round reads its sizes
+// and decisions from the device state, so one capture serves every round
+// with the same arguments.  It is taken once the first round has allocated
+// every buffer the round uses, on the context's private capture stream
+// (nothing runs there), and again after a rebuild between rounds; the graphs
+// are launched on the context's stream.  A single cloud's round is one
+// graph.  A batch's round is two, one for each part around the budget cut,
+// which sizes its sort on the host and runs eagerly between them (its
+// scratch slots are not among those the graphs hold).  A failed capture
+// leaves that part eager.
 struct RoundGraph {
     hipGraphExec_t exec = nullptr;
     ~RoundGraph() { reset(); }
@@ -1320,8 +1338,8 @@ struct RoundGraph {
     }
 };
 
-template <int K>
-void capture_round(Ctx* c, RoundArrays& a, const GridView& g, const GridView& gs, RoundGraph* rg) {
+template <class Launch>
+void capture(Ctx* c, RoundGraph* rg, Launch launch) {
     rg->reset();
     hipStream_t run = c->stream;
     if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -1329,7 +1347,7 @@ void capture_round(Ctx* c, RoundArrays& a, const GridView& g, const GridView& gs
         return;
     }
     c->stream = c->cap_stream;
-    const int rc = launch_round<K>(c, a, g, gs);
+    const int rc = launch();
     c->stream = run;
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
@@ -1348,15 +1366,31 @@ int run_rounds(Ctx* c, RoundArrays& a, const GridView& g, uint32_t n) {
     int rc = build_alive_view(c, a, g, &gs);
     if (rc) return rc;
     uint32_t view_alive = n;
-    RoundGraph rg;
-    const bool graphs = a.nseg == 1 && !c->eager && c->cap_stream;
+    RoundGraph rg, rgb;  // the round (a batch: its part before the budget cut) and a batch's part after it
+    const bool graphs = !c->eager && c->cap_stream;
+    const bool split = a.nseg > 1;
     for (uint64_t it = 0;; it++) {
-        if (rg.exec) {
-            PDD_HIP(c, hipGraphLaunch(rg.exec, c->stream));
-            c->stats[14]++;
+        if (!split) {
+            if (rg.exec) {
+                PDD_HIP(c, hipGraphLaunch(rg.exec, c->stream));
+                c->stats[14]++;
+            } else if ((rc = launch_round<K>(c, a, g, gs))) {
+                return rc;
+            }
         } else {
-            rc = launch_round<K>(c, a, g, gs);
-            if (rc) return rc;
+            if (rg.exec) {
+                PDD_HIP(c, hipGraphLaunch(rg.exec, c->stream));
+                c->stats[14]++;
+            } else {
+                launch_round_a(c, a);
+                PDD_HIP(c, hipGetLastError());
+            }
+            if ((rc = segment_budgets(c, a))) return rc;
+            if (rgb.exec) {
+                PDD_HIP(c, hipGraphLaunch(rgb.exec, c->stream));
+            } else if ((rc = launch_round_b<K>(c, a, g, gs))) {
+                return rc;
+            }
         }
         PDD_HIP(c, hipMemcpyAsync(hst, a.st, sizeof(RoundDev), hipMemcpyDeviceToHost, c->stream));
         PDD_HIP(c, hipStreamSynchronize(c->stream));
@@ -1386,14 +1420,26 @@ int run_rounds(Ctx* c, RoundArrays& a, const GridView& g, uint32_t n) {
             if ((rc = build_reverse(c, a, n, a.alive_list[hst->apar], hst->n_list))) return rc;
             c->stats[3]++;
             rg.reset();
+            rgb.reset();
         }
         // re-pack the alive search view once a fifth of its points are gone
         if ((uint64_t)hst->n_alive_new * 5 < (uint64_t)view_alive * 4) {
             if ((rc = build_alive_view(c, a, g, &gs))) return rc;
             view_alive = hst->n_alive_new;
             rg.reset();
+            rgb.reset();
         }
-        if (graphs && !rg.exec) capture_round<K>(c, a, g, gs, &rg);
+        if (graphs && !rg.exec) {
+            if (!split) {
+                capture(c, &rg, [&] { return launch_round<K>(c, a, g, gs); });
+            } else {
+                capture(c, &rg, [&] {
+                    launch_round_a(c, a);
+                    return PDD_OK;
+                });
+                capture(c, &rgb, [&] { return launch_round_b<K>(c, a, g, gs); });
+            }
+        }
         if (it > (uint64_t)n + 16) {
             c->err = "round loop made no progress";
             return PDD_EINTERNAL;

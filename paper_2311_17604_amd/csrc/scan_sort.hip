@@ -277,9 +277,10 @@ int iota_u32(Ctx* c, uint32_t* p, uint32_t count) {
     return PDD_OK;
 }
 
-// Scratch slots 40..47 are reserved for the scan's partial sums (one per
-// recursion level).
-static int scan_level(Ctx* c, const uint32_t* in, uint32_t* out, uint32_t count, uint32_t* total_dev, int level) {
+// The scan's partial sums take scratch slots slot0, slot0 + 1, ... (one
+// per recursion level, at most `levels`): 40..47 by default.
+static int scan_level(Ctx* c, const uint32_t* in, uint32_t* out, uint32_t count, uint32_t* total_dev, int level,
+                      int slot0, int levels) {
     if (count == 0) {
         if (total_dev) {
             hipLaunchKernelGGL(set_zero_k, dim3(1), dim3(1), 0, c->stream, total_dev);
@@ -293,13 +294,13 @@ static int scan_level(Ctx* c, const uint32_t* in, uint32_t* out, uint32_t count,
         PDD_HIP(c, hipGetLastError());
         return PDD_OK;
     }
-    if (level >= 8) return PDD_EINTERNAL;
-    uint32_t* part = (uint32_t*)scratch(c, 40 + level, (size_t)nb * 2 * sizeof(uint32_t));
+    if (level >= levels) return PDD_EINTERNAL;
+    uint32_t* part = (uint32_t*)scratch(c, slot0 + level, (size_t)nb * 2 * sizeof(uint32_t));
     if (!part) return PDD_ENOMEM;
     uint32_t* part_ex = part + nb;
     hipLaunchKernelGGL(scan_partials, dim3(nb), dim3(kBlock), 0, c->stream, in, count, part);
     PDD_HIP(c, hipGetLastError());
-    int rc = scan_level(c, part, part_ex, nb, nullptr, level + 1);
+    int rc = scan_level(c, part, part_ex, nb, nullptr, level + 1, slot0, levels);
     if (rc) return rc;
     hipLaunchKernelGGL(scan_tiles, dim3(nb), dim3(kBlock), 0, c->stream, in, out, count, part_ex, total_dev);
     PDD_HIP(c, hipGetLastError());
@@ -307,7 +308,12 @@ static int scan_level(Ctx* c, const uint32_t* in, uint32_t* out, uint32_t count,
 }
 
 int exclusive_scan_u32(Ctx* c, const uint32_t* in, uint32_t* out, uint32_t count, uint32_t* total_dev) {
-    return scan_level(c, in, out, count, total_dev, 0);
+    return scan_level(c, in, out, count, total_dev, 0, 40, 8);
+}
+
+int exclusive_scan_u32_at(Ctx* c, const uint32_t* in, uint32_t* out, uint32_t count, uint32_t* total_dev,
+                          int slot0, int levels) {
+    return scan_level(c, in, out, count, total_dev, 0, slot0, levels);
 }
 
 // out[i] = in[0] + ... + in[i-1] in 64 bits, for i < count.  Scratch slot 51

@@ -275,7 +275,7 @@ def quality(ctx: Context, xyz, r2, with_counts: bool = True):
 
 def decimate_batch(ctx: Context, xyz, offsets, keeps, k: int, b: int = 0, voxel_log2: int = 0,
                    round_frac: float = 0.0, check: bool = False, with_order: bool = True, timing: bool = False,
-                   progress: bool = False, round_blocks: int = 0):
+                   progress: bool = False, round_blocks: int = 0, eager: bool = False):
     """Independent clouds decimated together: cloud s is rows
     offsets[s]:offsets[s+1] of xyz and keeps keeps[s] points.  Returns
     (kept, order, order_cost), each the clouds' results one after another,
@@ -295,7 +295,7 @@ def decimate_batch(ctx: Context, xyz, offsets, keeps, k: int, b: int = 0, voxel_
     order_cost = torch.empty(m, dtype=torch.int64, device=pts.device) if with_order else None
     o = Opts(k=k, b=b, voxel_log2=voxel_log2, round_frac=round_frac, point_stride=stride,
              flags=(PDD_F_CHECK if check else 0) | (PDD_F_TIMING if timing else 0)
-             | (PDD_F_PROGRESS if progress else 0), round_blocks=round_blocks)
+             | (PDD_F_PROGRESS if progress else 0) | (PDD_F_EAGER if eager else 0), round_blocks=round_blocks)
     ctx._check(ctx.lib.pdd_decimate_batch(ctx.h, _ptr(pts), off.ctypes.data_as(ctypes.c_void_p), nscan,
                                           kp.ctypes.data_as(ctypes.c_void_p), ctypes.byref(o), _ptr(kept),
                                           _ptr(order), _ptr(order_cost)), "pdd_decimate_batch")

@@ -55,6 +55,27 @@ def test_batch_random_clouds(gpu, oracle_mod, seed, k, frac):
     _check_against_oracle(oracle_mod, clouds, keeps, k, got)
 
 
+@pytest.mark.parametrize("frac", [0.01, 0.3])
+def test_batch_round_graphs_equal_eager(gpu, oracle_mod, frac):
+    # a batch's round is captured as two graphs around the budget cut (whose
+    # sort runs eagerly between them); the same batch launched kernel by
+    # kernel, and the oracle, agree, on one context with eager work between
+    rng = np.random.default_rng(11)
+    clouds, keeps = [], []
+    for s in range(24):
+        n = int(rng.integers(200, 3000))
+        clouds.append(scangen.random_cloud(n, int(rng.choice([20, 300, 5000])), int(rng.integers(0, 1 << 30))))
+        keeps.append(int(rng.integers(1, n // 2)))
+    for eager in (False, True, False):
+        got = _run_batch(gpu, clouds, keeps, 8, round_frac=frac, eager=eager)
+        st = gpu.stats()
+        _check_against_oracle(oracle_mod, clouds, keeps, 8, got)
+        if eager:
+            assert st["graph_rounds"] == 0
+        else:
+            assert 0 < st["graph_rounds"] <= st["rounds"], st
+
+
 def test_batch_scans_uneven(gpu, oracle_mod):
     # scans of very different sizes and densities, keep ratios 10-50%
     clouds, keeps = [], []
