@@ -72,7 +72,7 @@ int autotune(Ctx* c, const int32_t* d_xyz, int64_t n, int64_t keep, const pdd_op
     const int s_auto_sample = (int)c->stats[5];
     int dvox = 0;
     // coordinate descent: round share, list width, finest level
-    for (float f : {0.005f, 0.0025f, 0.00125f, 0.02f, 0.04f}) {
+    for (float f : {0.005f, 0.0025f, 0.00175f, 0.00125f, 0.02f, 0.04f}) {
         pdd_opts o = best;
         o.round_frac = f;
         float ms;
