@@ -182,8 +182,8 @@ def main():
         print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "copies": 4}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (DESIGN.md explains how it would "
-              "shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs a decimation on one GPU and has no "
+              "multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import torch
